@@ -1,0 +1,206 @@
+/*
+ * fdas.h -- C ABI of the MI355X (gfx950) Fourier Domain Acceleration Search
+ * correlation hot path.
+ *
+ * Method: S. Dimoudi and W. Armour, "Pulsar Acceleration Searches on the GPU
+ * for the Square Kilometre Array", arXiv:1511.07343.  Templates are computed
+ * once in an initialisation stage and every received series then goes through
+ * the per-series steps of Sec. 4: real-to-complex DFT, overlapped segments,
+ * segment DFT, complex multiply-scale by every template, inverse DFT, and
+ * power spectrum operations (powers with edge removal), which produce the
+ * f-fdot power plane of Sec. 2 (Fig. 1).  On top of that plane this library
+ * sums harmonics and reports thresholded local maxima as candidates.
+ *
+ * Conventions shared by every call
+ *   - Every call returns an fdas_status; FDAS_OK is 0, errors are negative.
+ *     fdas_last_error() gives a thread-local detail string for the last error
+ *     raised on the calling thread.  No C++ exception crosses this ABI.
+ *   - The caller owns every buffer it passes in; the library owns bank, plan
+ *     and server objects and frees them in the matching *_destroy call.
+ *   - "device" pointers are HIP device allocations on the current device;
+ *     "host" pointers are ordinary host memory.  hip_stream arguments are a
+ *     hipStream_t passed as void* (NULL = the default stream).
+ *   - Complex data is interleaved (re, im) float32 ("c64") unless stated.
+ *   - Series length N is a power of two in [2^10, 2^26]; the spectrum has
+ *     Nb = N/2 bins, bin 0 (DC) is zeroed and the Nyquist bin dropped.
+ *   - The f-fdot plane is float32[nz][Nb], template-major (row iz holds all
+ *     Nb frequency bins of template iz, contiguous in k).
+ */
+#ifndef FDAS_H
+#define FDAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fdas_status {
+    FDAS_OK = 0,
+    FDAS_E_INVAL = -1,    /* an argument is out of range or inconsistent          */
+    FDAS_E_NOMEM = -2,    /* device or host allocation failed / budget exceeded   */
+    FDAS_E_DEVICE = -3,   /* a HIP call failed; the plan is unusable afterwards   */
+    FDAS_E_OVERFLOW = -4, /* more candidates than capacity; *ncands = true count  */
+    FDAS_E_BUSY = -5,     /* server queue full                                    */
+    FDAS_E_TIMEOUT = -6   /* fdas_poll: nothing completed within the timeout      */
+} fdas_status;
+
+typedef struct fdas_bank_s fdas_bank;
+typedef struct fdas_plan_s fdas_plan_t;
+typedef struct fdas_server_s fdas_server;
+
+/* One candidate: a thresholded local maximum of an nharm-harmonic sum whose
+ * top harmonic sits at plane cell (iz, k).  r and z describe the fundamental:
+ * r = k / nharm bins, z = z(iz) / nharm bins with z(iz) = -zmax + iz * dz.
+ * power is the harmonic sum; sigma its Gaussian-equivalent single-trial
+ * significance (FP64 on the host). 40 bytes. */
+typedef struct fdas_cand {
+    int64_t k;
+    int32_t iz;
+    int32_t nharm;
+    double r;
+    double z;
+    float power;
+    float sigma;
+} fdas_cand;
+
+/* Input kinds for fdas_search. */
+enum {
+    FDAS_IN_SERIES_F32 = 0,              /* float32[N] time series                    */
+    FDAS_IN_SPECTRUM_C64 = 1,            /* c64[Nb] raw spectrum; library normalises  */
+    FDAS_IN_SPECTRUM_C64_NORMALISED = 2  /* c64[Nb] already normalised spectrum       */
+};
+
+/* Search options.  Zero-initialise and call fdas_default_opts() first. */
+typedef struct fdas_opts {
+    double sigma;                /* detection threshold, single-trial sigma (default 6)      */
+    int32_t nharm_max;           /* 1, 2, 4, 8 or 16 harmonics summed (default 16)           */
+    int32_t median_window;       /* normalisation block length W, 32..8192, pow2 (def. 1024) */
+    int64_t cand_capacity;       /* device candidate buffer entries (default 1<<20)          */
+    int32_t templates_per_block; /* templates per correlation workgroup, 0 = automatic       */
+    int32_t reserved;
+} fdas_opts;
+
+void fdas_default_opts(fdas_opts *opts);
+
+/* ---------------------------------------------------------------- templates
+ * Sec. 2: one inverse-filter template per drift trial z = -zmax + iz * dz,
+ * iz = 0 .. 2 zmax / dz.  Template taps are the conjugate of the Fourier
+ * response A(q, z) of a tone drifting by z bins, q = -h .. h, normalised to
+ * unit energy, computed in FP64 from the Fresnel-integral closed form.
+ * h = ceil(zmax / 2) + 16.  Host-only: no device memory is touched.
+ * Errors: FDAS_E_INVAL unless 0 <= zmax <= 1200, dz > 0, 2 zmax / dz an
+ * integer (to 1e-9) and the bank has at most 4801 templates. */
+fdas_status fdas_make_templates(double zmax, double dz, fdas_bank **out);
+int32_t fdas_bank_nz(const fdas_bank *bank);
+int32_t fdas_bank_halfwidth(const fdas_bank *bank);
+double fdas_bank_z(const fdas_bank *bank, int32_t iz);
+/* Copy template iz's 2h+1 taps (q = -h..h) as interleaved FP64 (re, im) into
+ * re_im_out[2 * (2h + 1)] (host).  FDAS_E_INVAL for a bad iz. */
+fdas_status fdas_bank_taps(const fdas_bank *bank, int32_t iz, double *re_im_out);
+void fdas_bank_destroy(fdas_bank *bank);
+
+/* ------------------------------------------------------------ significance
+ * Threshold reading of "n-sigma": thr solves Q(nharm, thr) = Phi_c(sigma),
+ * where Q(n, S) = exp(-S) sum_{i<n} S^i / i! is the survival function of a
+ * sum of n unit-mean exponential powers and Phi_c the Gaussian upper tail.
+ * fdas_significance inverts it.  Host-only, FP64. */
+fdas_status fdas_threshold(double sigma, int32_t nharm, double *thr);
+fdas_status fdas_significance(double power, int32_t nharm, double *sigma);
+
+/* -------------------------------------------------------------------- plan
+ * Per-series state for one (bank, nsamp, seg): the bank transformed to the
+ * segment domain (c64[nz][seg], each template wrapped circularly, DFT'd in
+ * FP64 and scaled by 1/seg -- the "scale" of the multiply step), and every
+ * device work buffer, allocated once.  seg is the overlap-save segment length
+ * (Sec. 2, Sec. 4 steps 3-6): a power of two in [256, 8192], >= 4h; each
+ * segment yields seg - 2h valid bins.  Needs a visible GPU (it allocates).
+ * Errors: INVAL (nsamp, seg, opts), NOMEM, DEVICE.  A plan is not
+ * thread-safe; calls on it are ordered on the stream they are given. */
+fdas_status fdas_plan(const fdas_bank *bank, int64_t nsamp, int32_t seg,
+                      const fdas_opts *opts, fdas_plan_t **out);
+int64_t fdas_plan_nbins(const fdas_plan_t *plan);
+int64_t fdas_plan_device_bytes(const fdas_plan_t *plan);
+void fdas_plan_destroy(fdas_plan_t *plan);
+
+/* One series through the whole hot path (Sec. 4 steps 2-7, then harmonic sum
+ * and peaks):
+ *   in_kind/in_dev  device input: float32[nsamp] series, or c64[Nb] spectrum
+ *                   (caller-owned, read-only).
+ *   plane_dev       NULL, or device float32[nz][Nb] that receives the plane.
+ *   cands_host      host array of cap entries; receives candidates sorted by
+ *                   (nharm, k, iz).  May be NULL when cap is 0.
+ *   ncands          receives the number of candidates found.
+ *   hip_stream      stream the work is ordered on; the call returns after the
+ *                   candidates are on the host (the plane, if requested, is
+ *                   complete when the stream is).
+ * Errors: INVAL, DEVICE, OVERFLOW (cap or cand_capacity too small: the first
+ * min(cap, found) candidates in sorted order of those captured are returned
+ * and *ncands holds the true count). */
+fdas_status fdas_search(fdas_plan_t *plan, int32_t in_kind, const void *in_dev,
+                        float *plane_dev, fdas_cand *cands_host, int64_t cap,
+                        int64_t *ncands, void *hip_stream);
+
+/* Stage timing (measurement hook).  While enabled, fdas_search records a HIP
+ * event pair around each stage on the stream the stage runs on and adds the
+ * elapsed times (ms) into per-stage totals: 0 real-input DFT, 1 unpack and
+ * block medians, 2 segment DFTs, 3 fused multiply / inverse DFT / power,
+ * 4 harmonic sum and peaks.  fdas_plan_stage_times copies the FDAS_NSTAGES
+ * totals and the number of searches timed; enabling resets them. */
+#define FDAS_NSTAGES 5
+fdas_status fdas_plan_enable_timing(fdas_plan_t *plan, int32_t enable);
+fdas_status fdas_plan_stage_times(const fdas_plan_t *plan, double *ms_out, int64_t *nsearch_out);
+
+/* Several float32 series, possibly of different power-of-two lengths
+ * nsamp[i] <= the plan's nsamp, through the hot path on one stream with their
+ * stages overlapped (no plane is returned).  Trial i's candidates go to
+ * cands_host + sum_{j<i} cap[j], count to ncands[i].  Returns the first error,
+ * or OVERFLOW if any trial overflowed. */
+fdas_status fdas_search_batch(fdas_plan_t *plan, int32_t n, const float *const *series_dev,
+                              const int64_t *nsamp, fdas_cand *cands_host, const int64_t *cap,
+                              int64_t *ncands, void *hip_stream);
+
+/* Test hook: copy the last search's normalised spectrum (c64[Nb]) and block
+ * medians (double[ceil(Nb/W)]) to device buffers; either pointer may be NULL. */
+fdas_status fdas_plan_fetch_spectrum(fdas_plan_t *plan, void *spectrum_dev, double *medians_dev,
+                                     void *hip_stream);
+
+/* Batched unnormalised complex DFT of length 2^log2n (6 <= log2n <= 13) on
+ * device c64 data, in-place allowed: out[b][f] = sum_n in[b][n] e^{-+2 pi i n f / 2^log2n},
+ * sign - for inverse = 0, + for inverse = 1.  The workgroup DFT of the hot path. */
+fdas_status fdas_dft_c64(int32_t log2n, int32_t inverse, int64_t batch, const void *in_dev,
+                         void *out_dev, void *hip_stream);
+
+/* ------------------------------------------------------------------ server
+ * Continuous-batching request loop on one GPU.  The bank and per-length
+ * plans stay resident; requests (float32 host series, power-of-two lengths
+ * up to max_nsamp) are copied on submit, admitted while their device bytes
+ * fit hbm_budget (0 = 90% of free HBM at creation) and a slot is free, and run
+ * concurrently, one stream per slot.  Each result is what fdas_search returns
+ * for the same series alone. */
+fdas_status fdas_server_create(const fdas_bank *bank, int32_t seg, const fdas_opts *opts,
+                               int64_t max_nsamp, size_t hbm_budget, int32_t max_slots,
+                               fdas_server **out);
+/* Non-blocking; FDAS_E_BUSY if the pending queue holds 65536 requests. */
+fdas_status fdas_submit(fdas_server *server, const float *series_host, int64_t nsamp,
+                        uint64_t tag);
+/* Wait up to timeout_ms (< 0 = forever) for a completed request; fill its tag,
+ * candidates (sorted as fdas_search), count, and latency (submit -> result
+ * ready, seconds).  FDAS_E_TIMEOUT if none completed; a completed request's
+ * own error (e.g. OVERFLOW) is returned with its tag filled in. */
+fdas_status fdas_poll(fdas_server *server, uint64_t *tag, fdas_cand *cands, int64_t cap,
+                      int64_t *ncands, double *latency_s, int32_t timeout_ms);
+/* Requests submitted but not yet polled. */
+int64_t fdas_server_outstanding(const fdas_server *server);
+void fdas_server_destroy(fdas_server *server);
+
+/* --------------------------------------------------------------- errors */
+const char *fdas_strerror(fdas_status status);
+const char *fdas_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDAS_H */

@@ -1,0 +1,337 @@
+"""Python binding of libfdas, the MI355X FDAS correlation hot path.
+
+Argument marshalling only: every step of the search runs in the HIP kernels
+behind the C ABI declared in include/fdas.h.  PyTorch supplies device memory
+(tensors' data pointers) and streams (``torch.cuda.current_stream()``); the
+library raises ``ImportError`` when libfdas.so has not been built -- there is
+no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "FdasError", "load", "lib_path", "CAND_DTYPE", "Bank", "Plan", "Server",
+    "make_templates", "threshold", "significance", "dft_c64", "IN_SERIES", "IN_SPECTRUM",
+    "IN_SPECTRUM_NORMALISED",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libfdas.so")
+_lib = None
+
+IN_SERIES = 0
+IN_SPECTRUM = 1
+IN_SPECTRUM_NORMALISED = 2
+
+_c_i32, _c_i64, _c_dbl, _c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+
+
+class _Cand(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("iz", ctypes.c_int32), ("nharm", ctypes.c_int32),
+                ("r", ctypes.c_double), ("z", ctypes.c_double), ("power", ctypes.c_float),
+                ("sigma", ctypes.c_float)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_double), ("nharm_max", ctypes.c_int32),
+                ("median_window", ctypes.c_int32), ("cand_capacity", ctypes.c_int64),
+                ("templates_per_block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+CAND_DTYPE = np.dtype([("k", "<i8"), ("iz", "<i4"), ("nharm", "<i4"), ("r", "<f8"), ("z", "<f8"),
+                       ("power", "<f4"), ("sigma", "<f4")])
+assert CAND_DTYPE.itemsize == ctypes.sizeof(_Cand) == 40
+
+STATUS = {0: "FDAS_OK", -1: "FDAS_E_INVAL", -2: "FDAS_E_NOMEM", -3: "FDAS_E_DEVICE",
+          -4: "FDAS_E_OVERFLOW", -5: "FDAS_E_BUSY", -6: "FDAS_E_TIMEOUT"}
+
+
+class FdasError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libfdas.so (built by ``python -m paper_1511_07343_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run python -m paper_1511_07343_amd.build")
+    lib = ctypes.CDLL(_LIB_PATH)
+    P = ctypes.POINTER
+    sig = {
+        "fdas_default_opts": (None, [P(_Opts)]),
+        "fdas_make_templates": (_c_i32, [_c_dbl, _c_dbl, P(_c_vp)]),
+        "fdas_bank_nz": (_c_i32, [_c_vp]),
+        "fdas_bank_halfwidth": (_c_i32, [_c_vp]),
+        "fdas_bank_z": (_c_dbl, [_c_vp, _c_i32]),
+        "fdas_bank_taps": (_c_i32, [_c_vp, _c_i32, P(_c_dbl)]),
+        "fdas_bank_destroy": (None, [_c_vp]),
+        "fdas_threshold": (_c_i32, [_c_dbl, _c_i32, P(_c_dbl)]),
+        "fdas_significance": (_c_i32, [_c_dbl, _c_i32, P(_c_dbl)]),
+        "fdas_plan": (_c_i32, [_c_vp, _c_i64, _c_i32, P(_Opts), P(_c_vp)]),
+        "fdas_plan_nbins": (_c_i64, [_c_vp]),
+        "fdas_plan_device_bytes": (_c_i64, [_c_vp]),
+        "fdas_plan_destroy": (None, [_c_vp]),
+        "fdas_search": (_c_i32, [_c_vp, _c_i32, _c_vp, _c_vp, P(_Cand), _c_i64, P(_c_i64), _c_vp]),
+        "fdas_search_batch": (_c_i32, [_c_vp, _c_i32, P(_c_vp), P(_c_i64), P(_Cand), P(_c_i64),
+                                       P(_c_i64), _c_vp]),
+        "fdas_plan_fetch_spectrum": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp]),
+        "fdas_plan_enable_timing": (_c_i32, [_c_vp, _c_i32]),
+        "fdas_plan_stage_times": (_c_i32, [_c_vp, P(_c_dbl), P(_c_i64)]),
+        "fdas_dft_c64": (_c_i32, [_c_i32, _c_i32, _c_i64, _c_vp, _c_vp, _c_vp]),
+        "fdas_server_create": (_c_i32, [_c_vp, _c_i32, P(_Opts), _c_i64, ctypes.c_size_t, _c_i32,
+                                        P(_c_vp)]),
+        "fdas_submit": (_c_i32, [_c_vp, _c_vp, _c_i64, ctypes.c_uint64]),
+        "fdas_poll": (_c_i32, [_c_vp, P(ctypes.c_uint64), P(_Cand), _c_i64, P(_c_i64), P(_c_dbl),
+                               _c_i32]),
+        "fdas_server_outstanding": (_c_i64, [_c_vp]),
+        "fdas_server_destroy": (None, [_c_vp]),
+        "fdas_strerror": (ctypes.c_char_p, [_c_i32]),
+        "fdas_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, allow=()):
+    if status == 0 or status in allow:
+        return status
+    msg = load().fdas_last_error().decode(errors="replace")
+    raise FdasError(status, msg)
+
+
+def _stream_handle(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=1 << 20, templates_per_block=0):
+    o = _Opts()
+    load().fdas_default_opts(ctypes.byref(o))
+    o.sigma = float(sigma)
+    o.nharm_max = int(nharm_max)
+    o.median_window = int(median_window)
+    o.cand_capacity = int(cand_capacity)
+    o.templates_per_block = int(templates_per_block)
+    return o
+
+
+def _cands_to_numpy(buf, n: int) -> np.ndarray:
+    return np.frombuffer(ctypes.string_at(ctypes.addressof(buf), n * 40), dtype=CAND_DTYPE).copy() \
+        if n > 0 else np.zeros(0, dtype=CAND_DTYPE)
+
+
+def threshold(sigma: float, nharm: int) -> float:
+    out = ctypes.c_double()
+    _check(load().fdas_threshold(sigma, nharm, ctypes.byref(out)))
+    return out.value
+
+
+def significance(power: float, nharm: int) -> float:
+    out = ctypes.c_double()
+    _check(load().fdas_significance(power, nharm, ctypes.byref(out)))
+    return out.value
+
+
+class Bank:
+    """Template bank (host FP64): z = -zmax + iz dz, taps q = -h..h."""
+
+    def __init__(self, zmax: float, dz: float):
+        h = ctypes.c_void_p()
+        _check(load().fdas_make_templates(zmax, dz, ctypes.byref(h)))
+        self._h = h
+        self.zmax, self.dz = float(zmax), float(dz)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def nz(self) -> int:
+        return load().fdas_bank_nz(self._h)
+
+    @property
+    def h(self) -> int:
+        return load().fdas_bank_halfwidth(self._h)
+
+    def z(self, iz: int) -> float:
+        return load().fdas_bank_z(self._h, iz)
+
+    def taps(self, iz: int) -> np.ndarray:
+        n = 2 * self.h + 1
+        buf = (ctypes.c_double * (2 * n))()
+        _check(load().fdas_bank_taps(self._h, iz, buf))
+        a = np.frombuffer(buf, dtype=np.float64).copy()
+        return a[0::2] + 1j * a[1::2]
+
+    def close(self):
+        if self._h:
+            load().fdas_bank_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_templates(zmax: float, dz: float) -> Bank:
+    return Bank(zmax, dz)
+
+
+class Plan:
+    """Device-resident plan for one (bank, nsamp, seg)."""
+
+    def __init__(self, bank: Bank, nsamp: int, seg: int, **opts):
+        h = ctypes.c_void_p()
+        o = _opts(**opts)
+        _check(load().fdas_plan(bank.handle, int(nsamp), int(seg), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.bank = bank
+        self.nsamp, self.seg = int(nsamp), int(seg)
+        self.opts = o
+
+    @property
+    def nbins(self) -> int:
+        return load().fdas_plan_nbins(self._h)
+
+    @property
+    def device_bytes(self) -> int:
+        return load().fdas_plan_device_bytes(self._h)
+
+    def search(self, inp, kind: int = IN_SERIES, plane=None, cap: int = 65536, stream=None,
+               allow_overflow: bool = False):
+        """Run the hot path on a device tensor; returns (candidates, n_found)."""
+        buf = (_Cand * max(cap, 1))()
+        n = ctypes.c_int64()
+        st = load().fdas_search(self._h, kind, ctypes.c_void_p(inp.data_ptr()),
+                                ctypes.c_void_p(plane.data_ptr() if plane is not None else 0),
+                                buf, cap, ctypes.byref(n), _stream_handle(stream))
+        _check(st, allow=(-4,) if allow_overflow else ())
+        return _cands_to_numpy(buf, min(n.value, cap)), n.value
+
+    def search_batch(self, series: Sequence, caps: Optional[Sequence[int]] = None, stream=None):
+        """Several device float32 series; returns a list of candidate arrays."""
+        k = len(series)
+        caps = list(caps) if caps is not None else [65536] * k
+        ptrs = (ctypes.c_void_p * k)(*[s.data_ptr() for s in series])
+        ns = (ctypes.c_int64 * k)(*[int(s.numel()) for s in series])
+        cp = (ctypes.c_int64 * k)(*caps)
+        nc = (ctypes.c_int64 * k)()
+        buf = (_Cand * max(1, sum(caps)))()
+        _check(load().fdas_search_batch(self._h, k, ptrs, ns, buf, cp, nc, _stream_handle(stream)))
+        out, off = [], 0
+        allc = _cands_to_numpy(buf, sum(caps))
+        for i in range(k):
+            out.append(allc[off: off + min(nc[i], caps[i])].copy())
+            off += caps[i]
+        return out
+
+    def fetch_spectrum(self, spectrum=None, medians=None, stream=None):
+        _check(load().fdas_plan_fetch_spectrum(
+            self._h, ctypes.c_void_p(spectrum.data_ptr() if spectrum is not None else 0),
+            ctypes.c_void_p(medians.data_ptr() if medians is not None else 0), _stream_handle(stream)))
+
+    STAGES = ("r2c", "unpack_median", "segment_dft", "correlate", "harmonic_sum")
+
+    def enable_timing(self, enable: bool = True):
+        _check(load().fdas_plan_enable_timing(self._h, int(enable)))
+
+    def stage_times(self):
+        """(dict stage -> total ms, number of timed searches)."""
+        ms = (ctypes.c_double * 5)()
+        n = ctypes.c_int64()
+        _check(load().fdas_plan_stage_times(self._h, ms, ctypes.byref(n)))
+        return dict(zip(self.STAGES, list(ms))), n.value
+
+    def close(self):
+        if self._h:
+            load().fdas_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request loop (host series in, candidates out)."""
+
+    def __init__(self, bank: Bank, seg: int, max_nsamp: int, hbm_budget: int = 0, max_slots: int = 4,
+                 **opts):
+        h = ctypes.c_void_p()
+        o = _opts(**opts)
+        _check(load().fdas_server_create(bank.handle, int(seg), ctypes.byref(o), int(max_nsamp),
+                                         int(hbm_budget), int(max_slots), ctypes.byref(h)))
+        self._h = h
+        self.bank = bank
+
+    def submit(self, series: np.ndarray, tag: int):
+        x = np.ascontiguousarray(series, dtype=np.float32)
+        _check(load().fdas_submit(self._h, ctypes.c_void_p(x.ctypes.data), x.shape[0], int(tag)))
+
+    def poll(self, timeout_ms: int = -1, cap: int = 65536):
+        """Returns (tag, candidates, n_found, latency_s), or None on timeout."""
+        tag = ctypes.c_uint64()
+        n = ctypes.c_int64()
+        lat = ctypes.c_double()
+        buf = (_Cand * max(cap, 1))()
+        st = load().fdas_poll(self._h, ctypes.byref(tag), buf, cap, ctypes.byref(n), ctypes.byref(lat),
+                              int(timeout_ms))
+        if st == -6:
+            return None
+        _check(st)
+        return tag.value, _cands_to_numpy(buf, min(n.value, cap)), n.value, lat.value
+
+    @property
+    def outstanding(self) -> int:
+        return load().fdas_server_outstanding(self._h)
+
+    def close(self):
+        if self._h:
+            load().fdas_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def dft_c64(x, inverse: bool = False, out=None, stream=None):
+    """Batched unnormalised complex DFT along the last axis (length 2^6..2^13)."""
+    import torch
+    if x.dtype != torch.complex64 or not x.is_cuda:
+        raise TypeError("dft_c64 needs a complex64 CUDA tensor")
+    n = x.shape[-1]
+    log2n = int(n).bit_length() - 1
+    x = x.contiguous()
+    if out is None:
+        out = torch.empty_like(x)
+    batch = x.numel() // n
+    _check(load().fdas_dft_c64(log2n, int(inverse), batch, ctypes.c_void_p(x.data_ptr()),
+                               ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out

@@ -1,0 +1,142 @@
+// fdas_search_batch: many series through the hot path with consecutive trials
+// on two streams and two work buffers, so that one trial's memory-bound
+// harmonic sum runs beside the next trial's ALU-bound correlation.
+#include <algorithm>
+#include <string>
+
+#include "capi_internal.hpp"
+
+namespace fdas {
+
+static fdas_status ensure_batch_resources(fdas_plan_s *p) {
+    for (int i = 0; i < 2; ++i) {
+        if (!p->ws[i].nsamp) {
+            fdas_status s = alloc_workspace(p, p->ws[i], p->nsamp);
+            if (s != FDAS_OK) return s;
+        }
+        if (!p->aux[i]) {
+            hipError_t e = hipStreamCreateWithFlags(&p->aux[i], hipStreamNonBlocking);
+            if (e != hipSuccess) return hip_fail(p, e, "stream create");
+        }
+    }
+    for (hipEvent_t &ev : p->events) {
+        if (!ev) {
+            hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(p, e, "event create");
+        }
+    }
+    return FDAS_OK;
+}
+
+}  // namespace fdas
+
+using namespace fdas;
+
+extern "C" fdas_status fdas_search_batch(fdas_plan_t *plan, int32_t n, const float *const *series_dev,
+                                         const int64_t *nsamp, fdas_cand *cands_host, const int64_t *cap,
+                                         int64_t *ncands, void *hip_stream) {
+    if (!plan || n < 0 || (n > 0 && (!series_dev || !nsamp || !cap || !ncands))) {
+        set_error("bad batch arguments");
+        return FDAS_E_INVAL;
+    }
+    if (plan->broken) {
+        set_error("plan is unusable after a device error");
+        return FDAS_E_DEVICE;
+    }
+    int64_t total_cap = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!series_dev[i] || cap[i] < 0) {
+            set_error("bad series pointer or capacity in batch");
+            return FDAS_E_INVAL;
+        }
+        fdas_status s = check_nsamp(nsamp[i], plan->S, plan->h);
+        if (s != FDAS_OK) return s;
+        if (nsamp[i] > plan->nsamp) {
+            set_error("batch series longer than the plan's nsamp");
+            return FDAS_E_INVAL;
+        }
+        total_cap += cap[i];
+    }
+    if (total_cap > 0 && !cands_host) {
+        set_error("cands_host is NULL");
+        return FDAS_E_INVAL;
+    }
+    if (n == 0) return FDAS_OK;
+    fdas_status s = ensure_batch_resources(plan);
+    if (s != FDAS_OK) return s;
+
+    hipStream_t user = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipEventRecord(plan->events[2], user);
+    if (e != hipSuccess) return hip_fail(plan, e, "event record");
+    for (int i = 0; i < 2; ++i) {
+        e = hipStreamWaitEvent(plan->aux[i], plan->events[2], 0);
+        if (e != hipSuccess) return hip_fail(plan, e, "stream wait");
+    }
+
+    std::vector<int64_t> offset(size_t(n) + 1, 0);
+    for (int32_t i = 0; i < n; ++i) offset[size_t(i) + 1] = offset[size_t(i)] + cap[i];
+
+    fdas_status first_err = FDAS_OK;
+    bool overflow = false;
+    // Finish trial j: its count is already copied (event ev[j % 2]); copy the
+    // records and convert them.
+    auto finish = [&](int32_t j) -> fdas_status {
+        const int slot = j % 2;
+        Workspace &ws = plan->ws[slot];
+        hipError_t ee = hipEventSynchronize(plan->events[slot]);
+        if (ee != hipSuccess) return hip_fail(plan, ee, "batch trial");
+        const uint32_t found = *ws.h_count;
+        const int64_t got = std::min<int64_t>(found, plan->opts.cand_capacity);
+        if (got > 0) {
+            ee = hipMemcpyAsync(ws.h_cands, ws.cands, size_t(got) * sizeof(DevCand), hipMemcpyDeviceToHost,
+                                plan->aux[slot]);
+            if (ee != hipSuccess) return hip_fail(plan, ee, "copy candidates");
+            ee = hipStreamSynchronize(plan->aux[slot]);
+            if (ee != hipSuccess) return hip_fail(plan, ee, "copy candidates");
+        }
+        fdas_status r = finish_candidates(plan, found, ws.h_cands, cands_host + offset[size_t(j)], cap[j],
+                                          &ncands[j]);
+        if (r == FDAS_E_OVERFLOW) {
+            overflow = true;
+            r = FDAS_OK;
+        }
+        return r;
+    };
+
+    for (int32_t i = 0; i < n && first_err == FDAS_OK; ++i) {
+        const int slot = i % 2;
+        if (i >= 2) {
+            first_err = finish(i - 2);
+            if (first_err != FDAS_OK) break;
+        }
+        Workspace &ws = plan->ws[slot];
+        const Geometry g = make_geometry(nsamp[i], plan->S, plan->h, plan->W);
+        first_err = enqueue_search(plan, ws, g, FDAS_IN_SERIES_F32, series_dev[i], ws.plane, ws.cands, ws.count,
+                                   plan->aux[slot]);
+        if (first_err != FDAS_OK) break;
+        e = hipMemcpyAsync(ws.h_count, ws.count, 4, hipMemcpyDeviceToHost, plan->aux[slot]);
+        if (e != hipSuccess) {
+            first_err = hip_fail(plan, e, "copy candidate count");
+            break;
+        }
+        e = hipEventRecord(plan->events[slot], plan->aux[slot]);
+        if (e != hipSuccess) {
+            first_err = hip_fail(plan, e, "event record");
+            break;
+        }
+    }
+    if (first_err == FDAS_OK) {
+        for (int32_t j = std::max(0, n - 2); j < n && first_err == FDAS_OK; ++j) first_err = finish(j);
+    }
+    // order the user's stream after everything enqueued here
+    for (int i = 0; i < 2; ++i) {
+        if (hipEventRecord(plan->events[2 + (i & 1)], plan->aux[i]) == hipSuccess)
+            (void)hipStreamWaitEvent(user, plan->events[2 + (i & 1)], 0);
+    }
+    if (first_err != FDAS_OK) return first_err;
+    if (overflow) {
+        set_error("candidate capacity exceeded in a batch trial");
+        return FDAS_E_OVERFLOW;
+    }
+    return FDAS_OK;
+}

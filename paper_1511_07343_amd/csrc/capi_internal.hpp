@@ -1,0 +1,99 @@
+// Internal state behind the C ABI: bank, plan, work buffers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fdas.h"
+#include "host_math.hpp"
+#include "kernels.hpp"
+
+struct fdas_bank_s {
+    double zmax = 0.0, dz = 1.0;
+    int32_t nz = 0, h = 0;
+    std::vector<fdas::cd> taps;  // nz x (2h+1), tap q at column q + h
+};
+
+namespace fdas {
+
+// Per-length geometry.
+struct Geometry {
+    int64_t nsamp = 0, nb = 0, L = 0, nseg = 0, nblk = 0;
+};
+
+// Device buffers for one series in flight (sized for `nsamp`).
+struct Workspace {
+    int64_t nsamp = 0;
+    float2 *Z = nullptr;     // complex DFT of the packed series, M = nsamp/2
+    float2 *work = nullptr;  // four-step scratch, M
+    float2 *X = nullptr;     // real-input spectrum, nb bins
+    double *med = nullptr;   // block medians of |X|^2
+    float2 *seg = nullptr;   // segment spectra, nseg x S
+    float *plane = nullptr;  // f-fdot plane, nz x nb
+    DevCand *cands = nullptr;
+    uint32_t *count = nullptr;
+    DevCand *h_cands = nullptr;  // pinned host copies
+    uint32_t *h_count = nullptr;
+};
+
+}  // namespace fdas
+
+struct fdas_plan_s {
+    fdas_opts opts{};
+    double zmax = 0.0, dz = 1.0;
+    int32_t nz = 0, h = 0, izc = 0, S = 0, log2s = 0, W = 1024, tpb = 13;
+    int64_t nsamp = 0;
+    int device = 0;
+    double thr_d[5] = {};
+    float thr_f[5] = {};
+    float2 *d_bank = nullptr;  // nz x S, segment domain, scaled by 1/S
+    std::array<fdas::Workspace, 2> ws{};
+    std::array<hipStream_t, 2> aux{};
+    std::array<hipEvent_t, 4> events{};
+    bool broken = false;
+    // stage timing (fdas_plan_enable_timing)
+    bool timing = false;
+    std::array<hipEvent_t, 6> tev{};
+    std::array<double, 5> stage_ms{};
+    int64_t timed = 0;
+    // last search, for the inspection hook
+    const float2 *last_X = nullptr;
+    const double *last_med = nullptr;
+    int64_t last_nb = 0;
+};
+
+namespace fdas {
+
+extern thread_local std::string g_last_error;
+void set_error(const std::string &msg);
+fdas_status hip_fail(fdas_plan_s *plan, hipError_t e, const char *what);
+fdas_status validate_opts(const fdas_opts &o);
+fdas_status check_nsamp(int64_t nsamp, int32_t seg, int32_t h);
+Geometry make_geometry(int64_t nsamp, int32_t S, int32_t h, int32_t W);
+int64_t series_bytes(const Geometry &g, int32_t S, int32_t nz);
+fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp);
+void destroy_workspace(Workspace &ws);
+fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &g, int32_t in_kind,
+                           const void *in_dev, float *plane, DevCand *dcands, uint32_t *dcount, hipStream_t st,
+                           bool timed = false);
+fdas_status accumulate_timing(fdas_plan_s *p);
+fdas_status finish_candidates(const fdas_plan_s *p, uint32_t found, const DevCand *hc, fdas_cand *out,
+                              int64_t cap, int64_t *ncands);
+// Plan without work buffers: options, thresholds, bank in the segment domain.
+fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, const fdas_opts *opts,
+                           fdas_plan_s **out);
+fdas_status collect(fdas_plan_s *p, Workspace &ws, fdas_cand *out, int64_t cap, int64_t *ncands, hipStream_t st);
+
+// Templates per correlation workgroup: about 13, with the number of template
+// blocks rounded up to a multiple of the 8 XCDs.
+inline int32_t default_tpb(int32_t nz) {
+    int64_t nzb = (nz + 12) / 13;
+    nzb = ((nzb + 7) / 8) * 8;
+    return int32_t((nz + nzb - 1) / nzb);
+}
+
+}  // namespace fdas

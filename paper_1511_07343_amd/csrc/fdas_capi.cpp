@@ -1,0 +1,574 @@
+// C ABI of the FDAS library: template bank, plans, the per-series search, the
+// batched search and test hooks.  The serving loop lives in server.cpp.
+//
+// Per-series steps (Sec. 4 of Dimoudi & Armour): the series is already on the
+// device (step 1 is the caller's copy); real-to-complex DFT (step 2) plus the
+// block-median normalisation statistics; overlapped segments (step 3, folded
+// into the segment loader) and their DFTs (step 4); complex multiply by every
+// template, inverse DFT and power with edge removal (steps 5-7, one fused
+// kernel) into the f-fdot plane; then harmonic sums, thresholds and peaks.
+#include "capi_internal.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+namespace fdas {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+static bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+static int ilog2(int64_t v) {
+    int l = 0;
+    while ((int64_t(1) << l) < v) ++l;
+    return l;
+}
+
+fdas_status hip_fail(fdas_plan_s *plan, hipError_t e, const char *what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    if (plan) plan->broken = true;
+    return FDAS_E_DEVICE;
+}
+
+fdas_status validate_opts(const fdas_opts &o) {
+    if (!(o.sigma > -30.0 && o.sigma < 1000.0)) {
+        set_error("opts.sigma out of range");
+        return FDAS_E_INVAL;
+    }
+    if (!(o.nharm_max == 1 || o.nharm_max == 2 || o.nharm_max == 4 || o.nharm_max == 8 || o.nharm_max == 16)) {
+        set_error("opts.nharm_max must be 1, 2, 4, 8 or 16");
+        return FDAS_E_INVAL;
+    }
+    if (!is_pow2(o.median_window) || o.median_window < 32 || o.median_window > 8192) {
+        set_error("opts.median_window must be a power of two in [32, 8192]");
+        return FDAS_E_INVAL;
+    }
+    if (o.cand_capacity < 1 || o.cand_capacity > (int64_t(1) << 28)) {
+        set_error("opts.cand_capacity must be in [1, 2^28]");
+        return FDAS_E_INVAL;
+    }
+    if (o.templates_per_block < 0 || o.templates_per_block > 4096) {
+        set_error("opts.templates_per_block must be in [0, 4096]");
+        return FDAS_E_INVAL;
+    }
+    return FDAS_OK;
+}
+
+fdas_status check_nsamp(int64_t nsamp, int32_t seg, int32_t h) {
+    if (!is_pow2(nsamp) || nsamp < 1024 || nsamp > (int64_t(1) << 26)) {
+        set_error("nsamp must be a power of two in [2^10, 2^26]");
+        return FDAS_E_INVAL;
+    }
+    (void)seg;
+    (void)h;
+    return FDAS_OK;
+}
+
+// Geometry of one series length under a plan's segment length.
+Geometry make_geometry(int64_t nsamp, int32_t S, int32_t h, int32_t W) {
+    Geometry g;
+    g.nsamp = nsamp;
+    g.nb = nsamp / 2;
+    g.L = S - 2 * h;
+    g.nseg = (g.nb + g.L - 1) / g.L;
+    g.nblk = (g.nb + W - 1) / W;
+    return g;
+}
+
+// Device bytes of the per-series buffers (spectrum scratch, medians, segment
+// spectra, plane) for a given geometry.
+int64_t series_bytes(const Geometry &g, int32_t S, int32_t nz) {
+    const int64_t M = g.nb;
+    return 3 * M * 8 + g.nblk * 8 + g.nseg * int64_t(S) * 8 + int64_t(nz) * g.nb * 4;
+}
+
+// Run the whole per-series path on `st`, writing the plane into `plane` and
+// candidates into the plan's device buffers (count at *dcount).
+fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &g, int32_t in_kind,
+                           const void *in_dev, float *plane, DevCand *dcands, uint32_t *dcount,
+                           hipStream_t st, bool timed) {
+    hipError_t e;
+    const float2 *X = nullptr;
+    const double *med = nullptr;
+    // event i is recorded before stage i (and event 5 after the last stage)
+    auto mark = [&](int i) -> hipError_t { return timed ? hipEventRecord(p->tev[size_t(i)], st) : hipSuccess; };
+    if ((e = mark(0)) != hipSuccess) return hip_fail(p, e, "timing event");
+    if (in_kind == FDAS_IN_SERIES_F32) {
+        e = launch_r2c_packed(static_cast<const float *>(in_dev), g.nsamp, ws.Z, ws.work, st);
+        if (e != hipSuccess) return hip_fail(p, e, "real-input DFT");
+        if ((e = mark(1)) != hipSuccess) return hip_fail(p, e, "timing event");
+        e = launch_unpack_median(ws.Z, g.nsamp, ws.X, ws.med, p->W, st);
+        if (e != hipSuccess) return hip_fail(p, e, "unpack/median");
+        X = ws.X;
+        med = ws.med;
+    } else if (in_kind == FDAS_IN_SPECTRUM_C64) {
+        if ((e = mark(1)) != hipSuccess) return hip_fail(p, e, "timing event");
+        X = static_cast<const float2 *>(in_dev);
+        e = launch_median(X, g.nb, ws.med, p->W, st);
+        if (e != hipSuccess) return hip_fail(p, e, "median");
+        med = ws.med;
+    } else {
+        if ((e = mark(1)) != hipSuccess) return hip_fail(p, e, "timing event");
+        X = static_cast<const float2 *>(in_dev);
+    }
+    if ((e = mark(2)) != hipSuccess) return hip_fail(p, e, "timing event");
+    e = launch_segfft(X, med, p->W, g.nb, p->log2s, p->h, g.nseg, ws.seg, st);
+    if (e != hipSuccess) return hip_fail(p, e, "segment DFT");
+    if ((e = mark(3)) != hipSuccess) return hip_fail(p, e, "timing event");
+    e = launch_correlate(ws.seg, p->d_bank, p->nz, p->tpb, g.nb, p->log2s, p->h, g.nseg, plane, st);
+    if (e != hipSuccess) return hip_fail(p, e, "correlate");
+    if ((e = mark(4)) != hipSuccess) return hip_fail(p, e, "timing event");
+    e = launch_zero_u32(dcount, 1, st);
+    if (e != hipSuccess) return hip_fail(p, e, "zero counter");
+    e = launch_harmsum(plane, p->nz, g.nb, p->izc, p->opts.nharm_max, p->thr_f, dcands, dcount,
+                       uint32_t(p->opts.cand_capacity), st);
+    if (e != hipSuccess) return hip_fail(p, e, "harmonic sum");
+    if ((e = mark(5)) != hipSuccess) return hip_fail(p, e, "timing event");
+    p->last_X = X;
+    p->last_med = med;
+    p->last_nb = g.nb;
+    return FDAS_OK;
+}
+
+// Add the stage times of the last timed search (its events have completed).
+fdas_status accumulate_timing(fdas_plan_s *p) {
+    for (int i = 0; i < 5; ++i) {
+        float ms = 0.f;
+        hipError_t e = hipEventElapsedTime(&ms, p->tev[size_t(i)], p->tev[size_t(i) + 1]);
+        if (e != hipSuccess) return hip_fail(p, e, "stage timing");
+        p->stage_ms[size_t(i)] += ms;
+    }
+    ++p->timed;
+    return FDAS_OK;
+}
+
+// Turn device records into sorted fdas_cand entries.
+fdas_status finish_candidates(const fdas_plan_s *p, uint32_t found, const DevCand *hc, fdas_cand *out,
+                              int64_t cap, int64_t *ncands) {
+    const int64_t got = std::min<int64_t>(found, p->opts.cand_capacity);
+    std::vector<DevCand> v(hc, hc + got);
+    std::sort(v.begin(), v.end(), [](const DevCand &a, const DevCand &b) {
+        if (a.nharm != b.nharm) return a.nharm < b.nharm;
+        if (a.k != b.k) return a.k < b.k;
+        return a.iz < b.iz;
+    });
+    const int64_t nout = std::min<int64_t>(got, cap);
+    for (int64_t i = 0; i < nout; ++i) {
+        const DevCand &c = v[size_t(i)];
+        fdas_cand &o = out[i];
+        o.k = c.k;
+        o.iz = c.iz;
+        o.nharm = c.nharm;
+        o.r = double(c.k) / double(c.nharm);
+        o.z = (-p->zmax + double(c.iz) * p->dz) / double(c.nharm);
+        o.power = c.power;
+        o.sigma = float(significance(double(c.power), c.nharm));
+    }
+    if (ncands) *ncands = found;
+    if (int64_t(found) > cap || int64_t(found) > p->opts.cand_capacity) {
+        set_error("candidate capacity exceeded");
+        return FDAS_E_OVERFLOW;
+    }
+    return FDAS_OK;
+}
+
+static void free_workspace(Workspace &ws) {
+    if (ws.Z) (void)hipFree(ws.Z);
+    if (ws.work) (void)hipFree(ws.work);
+    if (ws.X) (void)hipFree(ws.X);
+    if (ws.med) (void)hipFree(ws.med);
+    if (ws.seg) (void)hipFree(ws.seg);
+    if (ws.plane) (void)hipFree(ws.plane);
+    if (ws.cands) (void)hipFree(ws.cands);
+    if (ws.count) (void)hipFree(ws.count);
+    if (ws.h_cands) (void)hipHostFree(ws.h_cands);
+    if (ws.h_count) (void)hipHostFree(ws.h_count);
+    ws = Workspace{};
+}
+
+fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp) {
+    const Geometry g = make_geometry(nsamp, p->S, p->h, p->W);
+    const int64_t M = g.nb;
+    hipError_t e;
+#define FDAS_ALLOC(ptr, bytes)                                                  \
+    e = hipMalloc(reinterpret_cast<void **>(&(ptr)), size_t(bytes));            \
+    if (e != hipSuccess) {                                                      \
+        free_workspace(ws);                                                     \
+        set_error(std::string("hipMalloc ") + #ptr + ": " + hipGetErrorString(e)); \
+        return FDAS_E_NOMEM;                                                    \
+    }
+    FDAS_ALLOC(ws.Z, M * 8);
+    FDAS_ALLOC(ws.work, M * 8);
+    FDAS_ALLOC(ws.X, M * 8);
+    FDAS_ALLOC(ws.med, g.nblk * 8);
+    FDAS_ALLOC(ws.seg, g.nseg * int64_t(p->S) * 8);
+    FDAS_ALLOC(ws.plane, int64_t(p->nz) * g.nb * 4);
+    FDAS_ALLOC(ws.cands, p->opts.cand_capacity * int64_t(sizeof(DevCand)));
+    FDAS_ALLOC(ws.count, 64);
+#undef FDAS_ALLOC
+    e = hipHostMalloc(reinterpret_cast<void **>(&ws.h_cands), size_t(p->opts.cand_capacity) * sizeof(DevCand),
+                      hipHostMallocDefault);
+    if (e != hipSuccess) {
+        free_workspace(ws);
+        set_error("hipHostMalloc candidates");
+        return FDAS_E_NOMEM;
+    }
+    e = hipHostMalloc(reinterpret_cast<void **>(&ws.h_count), 64, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        free_workspace(ws);
+        set_error("hipHostMalloc counter");
+        return FDAS_E_NOMEM;
+    }
+    ws.nsamp = nsamp;
+    return FDAS_OK;
+}
+
+void destroy_workspace(Workspace &ws) { free_workspace(ws); }
+
+// Candidates of a search enqueued on st: counter, then records, to the host.
+fdas_status collect(fdas_plan_s *p, Workspace &ws, fdas_cand *out, int64_t cap, int64_t *ncands,
+                    hipStream_t st) {
+    hipError_t e = hipMemcpyAsync(ws.h_count, ws.count, 4, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_fail(p, e, "copy candidate count");
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(p, e, "search");
+    const uint32_t found = *ws.h_count;
+    const int64_t got = std::min<int64_t>(found, p->opts.cand_capacity);
+    if (got > 0) {
+        e = hipMemcpyAsync(ws.h_cands, ws.cands, size_t(got) * sizeof(DevCand), hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return hip_fail(p, e, "copy candidates");
+        e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(p, e, "copy candidates");
+    }
+    return finish_candidates(p, found, ws.h_cands, out, cap, ncands);
+}
+
+
+fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, const fdas_opts *opts,
+                           fdas_plan_s **out) {
+    *out = nullptr;
+    if (!bank) {
+        set_error("bank is NULL");
+        return FDAS_E_INVAL;
+    }
+    fdas_opts o;
+    if (opts) o = *opts; else fdas_default_opts(&o);
+    fdas_status st = validate_opts(o);
+    if (st != FDAS_OK) return st;
+    st = check_nsamp(nsamp, seg, bank->h);
+    if (st != FDAS_OK) return st;
+    if (!is_pow2(seg) || seg < 256 || seg > 8192 || seg < 4 * bank->h) {
+        set_error("seg must be a power of two in [256, 8192] and >= 4h");
+        return FDAS_E_INVAL;
+    }
+    if (nsamp / 2 < int64_t(o.median_window)) {
+        set_error("nsamp / 2 must be at least the median window");
+        return FDAS_E_INVAL;
+    }
+    auto *p = new (std::nothrow) fdas_plan_s;
+    if (!p) {
+        set_error("out of host memory");
+        return FDAS_E_NOMEM;
+    }
+    p->opts = o;
+    p->zmax = bank->zmax;
+    p->dz = bank->dz;
+    p->nz = bank->nz;
+    p->h = bank->h;
+    p->izc = (bank->nz - 1) / 2;
+    p->S = seg;
+    p->log2s = ilog2(seg);
+    p->W = o.median_window;
+    p->nsamp = nsamp;
+    p->tpb = o.templates_per_block > 0 ? o.templates_per_block : default_tpb(bank->nz);
+    int levels = 0;
+    while ((1 << levels) < o.nharm_max) ++levels;
+    for (int l = 0; l < 5; ++l) {
+        p->thr_d[l] = l <= levels ? threshold(o.sigma, 1 << l) : INFINITY;
+        p->thr_f[l] = float(p->thr_d[l]);
+    }
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        set_error(std::string("no HIP device: ") + hipGetErrorString(e));
+        return FDAS_E_DEVICE;
+    }
+    // Template bank in the segment domain: taps wrapped circularly (q >= 0 at
+    // n = q, q < 0 at n = S + q), FP64 DFT, times 1/S, rounded to float32.
+    const int32_t S = seg, ntap = 2 * p->h + 1;
+    std::vector<float2> host(size_t(p->nz) * S);
+    std::vector<cd> t(S);
+    for (int32_t iz = 0; iz < p->nz; ++iz) {
+        std::fill(t.begin(), t.end(), cd(0.0, 0.0));
+        for (int32_t q = -p->h; q <= p->h; ++q) t[size_t((q + S) % S)] = bank->taps[size_t(iz) * ntap + (q + p->h)];
+        fft_inplace(t, -1);
+        for (int32_t f = 0; f < S; ++f) {
+            const cd v = t[size_t(f)] / double(S);
+            host[size_t(iz) * S + f] = make_float2(float(v.real()), float(v.imag()));
+        }
+    }
+    e = hipMalloc(reinterpret_cast<void **>(&p->d_bank), host.size() * sizeof(float2));
+    if (e != hipSuccess) {
+        delete p;
+        set_error(std::string("hipMalloc bank: ") + hipGetErrorString(e));
+        return FDAS_E_NOMEM;
+    }
+    e = hipMemcpy(p->d_bank, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(p->d_bank);
+        delete p;
+        set_error(std::string("upload bank: ") + hipGetErrorString(e));
+        return FDAS_E_DEVICE;
+    }
+    *out = p;
+    return FDAS_OK;
+}
+}  // namespace fdas
+
+using namespace fdas;
+
+extern "C" {
+
+void fdas_default_opts(fdas_opts *opts) {
+    if (!opts) return;
+    std::memset(opts, 0, sizeof(*opts));
+    opts->sigma = 6.0;
+    opts->nharm_max = 16;
+    opts->median_window = 1024;
+    opts->cand_capacity = int64_t(1) << 20;
+    opts->templates_per_block = 0;
+}
+
+fdas_status fdas_make_templates(double zmax, double dz, fdas_bank **out) {
+    if (!out) {
+        set_error("out is NULL");
+        return FDAS_E_INVAL;
+    }
+    *out = nullptr;
+    if (!(zmax >= 0.0 && zmax <= 1200.0) || !(dz > 0.0)) {
+        set_error("need 0 <= zmax <= 1200 and dz > 0");
+        return FDAS_E_INVAL;
+    }
+    const double ratio = 2.0 * zmax / dz;
+    const double rr = std::nearbyint(ratio);
+    if (std::fabs(ratio - rr) > 1e-9 * std::max(1.0, ratio) || rr > 4800.0) {
+        set_error("2 zmax / dz must be an integer <= 4800");
+        return FDAS_E_INVAL;
+    }
+    auto *b = new (std::nothrow) fdas_bank_s;
+    if (!b) {
+        set_error("out of host memory");
+        return FDAS_E_NOMEM;
+    }
+    b->zmax = zmax;
+    b->dz = dz;
+    b->nz = int32_t(rr) + 1;
+    b->h = template_halfwidth(zmax);
+    const int32_t ntap = 2 * b->h + 1;
+    b->taps.resize(size_t(b->nz) * ntap);
+    for (int32_t iz = 0; iz < b->nz; ++iz) template_taps(-zmax + double(iz) * dz, b->h, &b->taps[size_t(iz) * ntap]);
+    *out = b;
+    return FDAS_OK;
+}
+
+int32_t fdas_bank_nz(const fdas_bank *bank) { return bank ? bank->nz : 0; }
+int32_t fdas_bank_halfwidth(const fdas_bank *bank) { return bank ? bank->h : 0; }
+double fdas_bank_z(const fdas_bank *bank, int32_t iz) {
+    return bank ? -bank->zmax + double(iz) * bank->dz : 0.0;
+}
+
+fdas_status fdas_bank_taps(const fdas_bank *bank, int32_t iz, double *re_im_out) {
+    if (!bank || !re_im_out || iz < 0 || iz >= bank->nz) {
+        set_error("bad bank, output or template index");
+        return FDAS_E_INVAL;
+    }
+    const int32_t ntap = 2 * bank->h + 1;
+    for (int32_t i = 0; i < ntap; ++i) {
+        const cd v = bank->taps[size_t(iz) * ntap + i];
+        re_im_out[2 * i] = v.real();
+        re_im_out[2 * i + 1] = v.imag();
+    }
+    return FDAS_OK;
+}
+
+void fdas_bank_destroy(fdas_bank *bank) { delete bank; }
+
+fdas_status fdas_threshold(double sigma, int32_t nharm, double *thr) {
+    if (!thr || nharm < 1 || nharm > 64 || !(sigma > -30.0 && sigma < 1000.0)) {
+        set_error("bad threshold arguments");
+        return FDAS_E_INVAL;
+    }
+    *thr = threshold(sigma, nharm);
+    return FDAS_OK;
+}
+
+fdas_status fdas_significance(double power, int32_t nharm, double *sigma) {
+    if (!sigma || nharm < 1 || nharm > 64 || !(power >= 0.0) || !std::isfinite(power)) {
+        set_error("bad significance arguments");
+        return FDAS_E_INVAL;
+    }
+    *sigma = significance(power, nharm);
+    return FDAS_OK;
+}
+
+fdas_status fdas_plan(const fdas_bank *bank, int64_t nsamp, int32_t seg, const fdas_opts *opts,
+                      fdas_plan_t **out) {
+    if (!out) {
+        set_error("out is NULL");
+        return FDAS_E_INVAL;
+    }
+    *out = nullptr;
+    fdas_plan_s *p = nullptr;
+    fdas_status st = make_plan_core(bank, nsamp, seg, opts, &p);
+    if (st != FDAS_OK) return st;
+    st = alloc_workspace(p, p->ws[0], nsamp);
+    if (st != FDAS_OK) {
+        fdas_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return FDAS_OK;
+}
+
+int64_t fdas_plan_nbins(const fdas_plan_t *plan) { return plan ? plan->nsamp / 2 : 0; }
+
+int64_t fdas_plan_device_bytes(const fdas_plan_t *plan) {
+    if (!plan) return 0;
+    int64_t b = int64_t(plan->nz) * plan->S * 8;
+    for (const Workspace &ws : plan->ws)
+        if (ws.nsamp) b += series_bytes(make_geometry(ws.nsamp, plan->S, plan->h, plan->W), plan->S, plan->nz);
+    return b;
+}
+
+void fdas_plan_destroy(fdas_plan_t *plan) {
+    if (!plan) return;
+    for (Workspace &ws : plan->ws) destroy_workspace(ws);
+    for (hipStream_t &s : plan->aux) {
+        if (s) (void)hipStreamDestroy(s);
+        s = nullptr;
+    }
+    for (hipEvent_t &ev : plan->events) {
+        if (ev) (void)hipEventDestroy(ev);
+        ev = nullptr;
+    }
+    for (hipEvent_t &ev : plan->tev) {
+        if (ev) (void)hipEventDestroy(ev);
+        ev = nullptr;
+    }
+    if (plan->d_bank) (void)hipFree(plan->d_bank);
+    delete plan;
+}
+
+fdas_status fdas_search(fdas_plan_t *plan, int32_t in_kind, const void *in_dev, float *plane_dev,
+                        fdas_cand *cands_host, int64_t cap, int64_t *ncands, void *hip_stream) {
+    if (!plan || !in_dev || cap < 0 || (cap > 0 && !cands_host)) {
+        set_error("bad plan, input or candidate buffer");
+        return FDAS_E_INVAL;
+    }
+    if (in_kind < FDAS_IN_SERIES_F32 || in_kind > FDAS_IN_SPECTRUM_C64_NORMALISED) {
+        set_error("bad input kind");
+        return FDAS_E_INVAL;
+    }
+    if (plan->broken) {
+        set_error("plan is unusable after a device error");
+        return FDAS_E_DEVICE;
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    Workspace &ws = plan->ws[0];
+    const Geometry g = make_geometry(plan->nsamp, plan->S, plan->h, plan->W);
+    float *plane = plane_dev ? plane_dev : ws.plane;
+    const bool timed = plan->timing;
+    fdas_status s = enqueue_search(plan, ws, g, in_kind, in_dev, plane, ws.cands, ws.count, st, timed);
+    if (s != FDAS_OK) return s;
+    s = collect(plan, ws, cands_host, cap, ncands, st);
+    if (timed && (s == FDAS_OK || s == FDAS_E_OVERFLOW)) {
+        const fdas_status t = accumulate_timing(plan);
+        if (t != FDAS_OK) return t;
+    }
+    return s;
+}
+
+fdas_status fdas_plan_enable_timing(fdas_plan_t *plan, int32_t enable) {
+    if (!plan) {
+        set_error("plan is NULL");
+        return FDAS_E_INVAL;
+    }
+    for (hipEvent_t &ev : plan->tev) {
+        if (!ev) {
+            hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) return hip_fail(plan, e, "event create");
+        }
+    }
+    plan->timing = enable != 0;
+    plan->stage_ms.fill(0.0);
+    plan->timed = 0;
+    return FDAS_OK;
+}
+
+fdas_status fdas_plan_stage_times(const fdas_plan_t *plan, double *ms_out, int64_t *nsearch_out) {
+    if (!plan || !ms_out) {
+        set_error("plan or output is NULL");
+        return FDAS_E_INVAL;
+    }
+    for (int i = 0; i < FDAS_NSTAGES; ++i) ms_out[i] = plan->stage_ms[size_t(i)];
+    if (nsearch_out) *nsearch_out = plan->timed;
+    return FDAS_OK;
+}
+
+fdas_status fdas_plan_fetch_spectrum(fdas_plan_t *plan, void *spectrum_dev, double *medians_dev, void *hip_stream) {
+    if (!plan || !plan->last_X) {
+        set_error("no search has run on this plan");
+        return FDAS_E_INVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int64_t nb = plan->last_nb;
+    hipError_t e;
+    if (spectrum_dev) {
+        if (plan->last_med)
+            e = launch_normalise(plan->last_X, plan->last_med, plan->W, nb, static_cast<float2 *>(spectrum_dev), st);
+        else
+            e = hipMemcpyAsync(spectrum_dev, plan->last_X, size_t(nb) * 8, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail(plan, e, "fetch spectrum");
+    }
+    if (medians_dev && plan->last_med) {
+        e = hipMemcpyAsync(medians_dev, plan->last_med, size_t((nb + plan->W - 1) / plan->W) * 8,
+                           hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail(plan, e, "fetch medians");
+    }
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(plan, e, "fetch");
+    return FDAS_OK;
+}
+
+fdas_status fdas_dft_c64(int32_t log2n, int32_t inverse, int64_t batch, const void *in_dev, void *out_dev,
+                         void *hip_stream) {
+    if (log2n < 6 || log2n > 13 || batch < 0 || batch > 0x7fffffff || (batch > 0 && (!in_dev || !out_dev))) {
+        set_error("bad DFT arguments");
+        return FDAS_E_INVAL;
+    }
+    hipError_t e = launch_dft(log2n, inverse ? +1 : -1, batch, static_cast<const float2 *>(in_dev),
+                              static_cast<float2 *>(out_dev), static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(nullptr, e, "dft");
+    return FDAS_OK;
+}
+
+const char *fdas_strerror(fdas_status status) {
+    switch (status) {
+        case FDAS_OK: return "ok";
+        case FDAS_E_INVAL: return "invalid argument";
+        case FDAS_E_NOMEM: return "out of memory";
+        case FDAS_E_DEVICE: return "device error";
+        case FDAS_E_OVERFLOW: return "candidate capacity exceeded";
+        case FDAS_E_BUSY: return "queue full";
+        case FDAS_E_TIMEOUT: return "timed out";
+    }
+    return "unknown status";
+}
+
+const char *fdas_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

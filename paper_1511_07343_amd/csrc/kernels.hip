@@ -1,0 +1,490 @@
+// FDAS device kernels for gfx950 (CDNA4).  Steps follow Sec. 4 of Dimoudi &
+// Armour (arXiv:1511.07343): real-to-complex DFT (step 2), overlapped segments
+// and their DFTs (steps 3-4, the overlap copy folded into the segment loader),
+// complex multiply-scale by every template (step 5), inverse DFT (step 6) and
+// power with edge removal (step 7) fused into one kernel; then harmonic sums,
+// thresholds and local maxima on the resulting f-fdot plane.
+#include "fft_wg.hpp"
+#include "kernels.hpp"
+
+#include <cmath>
+
+namespace fdas {
+
+namespace {
+
+constexpr double kLn2 = 0.69314718055994530942;
+
+// Threads per workgroup for a transform of 2^log2s points.
+constexpr int fft_threads(int log2s) {
+    return log2s >= 12 ? 256 : log2s == 11 ? 128 : log2s >= 8 ? 64 : 32;
+}
+
+// 8 XCDs on MI355X; workgroups are dispatched to XCDs round-robin by index.
+constexpr int kXcds = 8;
+
+// ------------------------------------------------------------- plain DFT
+template <int LOG2S, int DIR>
+__global__ __launch_bounds__(fft_threads(LOG2S)) void k_dft(const float2 *__restrict__ in,
+                                                            float2 *__restrict__ out) {
+    using Sh = FftShape<LOG2S, fft_threads(LOG2S)>;
+    __shared__ float2 lds[Sh::LDS_FLOAT2];
+    const int t = threadIdx.x;
+    const int64_t base = int64_t(blockIdx.x) * Sh::S;
+    Twiddles<Sh, DIR> tw;
+    tw.init(t);
+    float2 v[Sh::R];
+#pragma unroll
+    for (int m = 0; m < Sh::R; ++m) v[m] = in[base + t + Sh::NT * m];
+    fft_wg<Sh, DIR>(v, lds, tw, t);
+#pragma unroll
+    for (int m = 0; m < Sh::R; ++m) out[base + t + Sh::NT * m] = v[m];
+}
+
+// ------------------------------------------------------- real input DFT
+// z[n] = x[2n] + i x[2n+1] is read as float2 directly from the series.
+
+// M = 2^LOG2M <= 8192: one workgroup.
+template <int LOG2M>
+__global__ __launch_bounds__(fft_threads(LOG2M)) void k_r2c_small(const float2 *__restrict__ z,
+                                                                  float2 *__restrict__ Z) {
+    using Sh = FftShape<LOG2M, fft_threads(LOG2M)>;
+    __shared__ float2 lds[Sh::LDS_FLOAT2];
+    const int t = threadIdx.x;
+    Twiddles<Sh, -1> tw;
+    tw.init(t);
+    float2 v[Sh::R];
+#pragma unroll
+    for (int m = 0; m < Sh::R; ++m) v[m] = z[t + Sh::NT * m];
+    fft_wg<Sh, -1>(v, lds, tw, t);
+#pragma unroll
+    for (int m = 0; m < Sh::R; ++m) Z[t + Sh::NT * m] = v[m];
+}
+
+// Four-step M = M1 * M2 (n = n2 + M2 n1, k = k1 + M1 k2).
+// Pass A, one workgroup per column n2: DFT over n1, times exp(-2 pi i n2 k1 / M),
+// stored at work[n2 + M2 k1].
+template <int LOG2M1>
+__global__ __launch_bounds__(fft_threads(LOG2M1)) void k_r2c_cols(const float2 *__restrict__ z,
+                                                                  float2 *__restrict__ work,
+                                                                  int log2m2) {
+    using Sh = FftShape<LOG2M1, fft_threads(LOG2M1)>;
+    __shared__ float2 lds[Sh::LDS_FLOAT2];
+    const int t = threadIdx.x;
+    const int64_t M2 = int64_t(1) << log2m2;
+    const int64_t M = M2 << LOG2M1;
+    const int64_t n2 = blockIdx.x;
+    Twiddles<Sh, -1> tw;
+    tw.init(t);
+    float2 v[Sh::R];
+#pragma unroll
+    for (int m = 0; m < Sh::R; ++m) v[m] = z[n2 + M2 * (t + Sh::NT * m)];
+    fft_wg<Sh, -1>(v, lds, tw, t);
+#pragma unroll
+    for (int m = 0; m < Sh::R; ++m) {
+        const int64_t k1 = t + Sh::NT * m;
+        const int64_t idx = (n2 * k1) & (M - 1);
+        double s, c;
+        sincospi(-2.0 * double(idx) / double(M), &s, &c);
+        const float2 w = make_float2(float(c), float(s));
+        work[n2 + M2 * k1] = cmul(v[m], w);
+    }
+}
+
+// Pass B, one workgroup per row k1: DFT over n2 -> Z[k1 + M1 k2].
+template <int LOG2M2>
+__global__ __launch_bounds__(fft_threads(LOG2M2)) void k_r2c_rows(const float2 *__restrict__ work,
+                                                                  float2 *__restrict__ Z,
+                                                                  int log2m1) {
+    using Sh = FftShape<LOG2M2, fft_threads(LOG2M2)>;
+    __shared__ float2 lds[Sh::LDS_FLOAT2];
+    const int t = threadIdx.x;
+    const int64_t k1 = blockIdx.x;
+    Twiddles<Sh, -1> tw;
+    tw.init(t);
+    float2 v[Sh::R];
+#pragma unroll
+    for (int m = 0; m < Sh::R; ++m) v[m] = work[(k1 << LOG2M2) + t + Sh::NT * m];
+    fft_wg<Sh, -1>(v, lds, tw, t);
+#pragma unroll
+    for (int m = 0; m < Sh::R; ++m) Z[k1 + (int64_t(t + Sh::NT * m) << log2m1)] = v[m];
+}
+
+// ------------------------------------------------------ medians of |X|^2
+// Ascending bitonic sort of W (power of two) floats in LDS.
+__device__ void bitonic_sort_lds(float *s, int W) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int size = 2; size <= W; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (int i = t; i < (W >> 1); i += nt) {
+                const int lo = 2 * stride * (i / stride) + (i % stride);
+                const int hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const float a = s[lo], b = s[hi];
+                if ((a > b) == asc) {
+                    s[lo] = b;
+                    s[hi] = a;
+                }
+            }
+        }
+    }
+    __syncthreads();
+}
+
+constexpr int kMedThreads = 256;
+constexpr int kMaxW = 8192;
+
+// Median of the sorted valid prefix of length w (mean of the middle pair for
+// even w), in FP64.
+__device__ __forceinline__ double median_sorted(const float *s, int w) {
+    return (w & 1) ? double(s[w >> 1]) : 0.5 * (double(s[(w >> 1) - 1]) + double(s[w >> 1]));
+}
+
+// One workgroup per block of W bins: X[k] from Z[k] and Z[M - k], then the
+// block's median power.
+__global__ __launch_bounds__(kMedThreads) void k_unpack_median(const float2 *__restrict__ Z,
+                                                               int64_t M, float2 *__restrict__ X,
+                                                               double *__restrict__ med, int W) {
+    __shared__ float s[kMaxW];
+    const int t = threadIdx.x;
+    const int64_t b0 = int64_t(blockIdx.x) * W;
+    const int w = int(min(int64_t(W), M - b0));
+    const double inv_n = 1.0 / double(2 * M);
+    for (int i = t; i < W; i += kMedThreads) {
+        float p = INFINITY;
+        if (i < w) {
+            const int64_t k = b0 + i;
+            float2 x = make_float2(0.f, 0.f);
+            if (k > 0) {
+                const float2 zk = Z[k];
+                const float2 zm = Z[M - k];
+                // E = (Z[k] + conj Z[M-k]) / 2,  O = (Z[k] - conj Z[M-k]) / (2i)
+                const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+                const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+                double sn, cs;
+                sincospi(-2.0 * double(k) * inv_n, &sn, &cs);
+                x = cadd(e, cmul(o, make_float2(float(cs), float(sn))));
+            }
+            X[k] = x;
+            p = cnorm(x);
+        }
+        s[i] = p;
+    }
+    bitonic_sort_lds(s, W);
+    if (t == 0) med[blockIdx.x] = median_sorted(s, w);
+}
+
+__global__ __launch_bounds__(kMedThreads) void k_median(const float2 *__restrict__ X, int64_t nb,
+                                                        double *__restrict__ med, int W) {
+    __shared__ float s[kMaxW];
+    const int t = threadIdx.x;
+    const int64_t b0 = int64_t(blockIdx.x) * W;
+    const int w = int(min(int64_t(W), nb - b0));
+    for (int i = t; i < W; i += kMedThreads) s[i] = i < w ? cnorm(X[b0 + i]) : INFINITY;
+    bitonic_sort_lds(s, W);
+    if (t == 0) med[blockIdx.x] = median_sorted(s, w);
+}
+
+// m(k): block medians joined linearly between block centres, flat outside.
+__device__ __forceinline__ double median_curve(const double *__restrict__ med, int64_t nblk, int W,
+                                               int64_t nb, int64_t g) {
+    const double c0 = 0.5 * double(min(int64_t(W), nb) - 1);
+    const int64_t wl = nb - (nblk - 1) * int64_t(W);
+    const double cl = double((nblk - 1) * int64_t(W)) + 0.5 * double(wl - 1);
+    const double x = double(g);
+    if (x <= c0 || nblk == 1) return med[0];
+    if (x >= cl) return med[nblk - 1];
+    const int64_t b = int64_t(floor((x - c0) / double(W)));
+    const double cb = c0 + double(b) * double(W);
+    const double cb1 = (b + 1 == nblk - 1) ? cl : cb + double(W);
+    return med[b] + (med[b + 1] - med[b]) * ((x - cb) / (cb1 - cb));
+}
+
+// -------------------------------------------------------- segment DFTs
+template <int LOG2S>
+__global__ __launch_bounds__(fft_threads(LOG2S)) void k_segfft(const float2 *__restrict__ X,
+                                                               const double *__restrict__ med,
+                                                               int W, int64_t nb, int h,
+                                                               float2 *__restrict__ segspec) {
+    using Sh = FftShape<LOG2S, fft_threads(LOG2S)>;
+    __shared__ float2 lds[Sh::LDS_FLOAT2];
+    const int t = threadIdx.x;
+    const int64_t s = blockIdx.x;
+    const int64_t L = Sh::S - 2 * h;
+    const int64_t g0 = s * L - h;
+    const int64_t nblk = (nb + W - 1) / W;
+    Twiddles<Sh, -1> tw;
+    tw.init(t);
+    float2 v[Sh::R];
+#pragma unroll
+    for (int m = 0; m < Sh::R; ++m) {
+        const int64_t g = g0 + t + Sh::NT * m;
+        float2 x = make_float2(0.f, 0.f);
+        if (g >= 0 && g < nb) {
+            x = X[g];
+            if (med) {
+                const double mk = median_curve(med, nblk, W, nb, g);
+                const float sc = mk > 0.0 ? float(sqrt(kLn2 / mk)) : 0.f;
+                x = make_float2(x.x * sc, x.y * sc);
+            }
+        }
+        v[m] = x;
+    }
+    fft_wg<Sh, -1>(v, lds, tw, t);
+#pragma unroll
+    for (int m = 0; m < Sh::R; ++m) segspec[s * Sh::S + t + Sh::NT * m] = v[m];
+}
+
+// Xhat = X sqrt(ln2 / m(k)) written out (inspection only; the search path
+// applies the same scale inside k_segfft's loader).
+__global__ __launch_bounds__(256) void k_normalise(const float2 *__restrict__ X, const double *__restrict__ med,
+                                                   int W, int64_t nb, float2 *__restrict__ out) {
+    const int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (g >= nb) return;
+    const int64_t nblk = (nb + W - 1) / W;
+    const double mk = median_curve(med, nblk, W, nb, g);
+    const float sc = mk > 0.0 ? float(sqrt(kLn2 / mk)) : 0.f;
+    const float2 x = X[g];
+    out[g] = make_float2(x.x * sc, x.y * sc);
+}
+
+// ----------------------------------------------- fused correlation kernel
+// Work item u = (template block tb, segment s), tb-major.  Workgroup i runs
+// item u = (i mod 8) * per + i div 8, so each XCD walks a contiguous range of
+// template blocks over all segments and keeps its templates in its own L2.
+template <int LOG2S>
+__global__ __launch_bounds__(fft_threads(LOG2S), 2) void k_correlate(
+    const float2 *__restrict__ segspec, const float2 *__restrict__ bank, int nz, int tpb, int64_t nb,
+    int h, int64_t nseg, int64_t total, int64_t per, float *__restrict__ plane) {
+    using Sh = FftShape<LOG2S, fft_threads(LOG2S)>;
+    __shared__ float2 lds[Sh::LDS_FLOAT2];
+    const int t = threadIdx.x;
+    const int64_t u = int64_t(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    if (u >= total) return;
+    const int64_t tb = u / nseg;
+    const int64_t s = u - tb * nseg;
+    const int64_t L = Sh::S - 2 * h;
+    const int iz0 = int(tb) * tpb;
+    const int iz1 = min(nz, iz0 + tpb);
+
+    Twiddles<Sh, +1> tw;
+    tw.init(t);
+    // The segment spectrum is re-read per template (from L2: consecutive
+    // workgroups of an XCD share it); keeping it in registers would spill.
+    const float2 *__restrict__ sp = segspec + s * Sh::S;
+
+    const int64_t kbase = s * L - h;  // plane column of segment point n is kbase + n
+    // columns [kbase + h, kend) of the plane come from this segment
+    const int nend = int(min(int64_t(Sh::S - h), nb - kbase));
+    for (int iz = iz0; iz < iz1; ++iz) {
+        // Keep the per-point offsets inside the loop: hoisting the 32 addresses
+        // of each operand out of it would cost more registers than recomputing.
+        int to = t;
+        asm volatile("" : "+v"(to));
+        const float2 *__restrict__ bz = bank + int64_t(iz) * Sh::S;
+        float2 v[Sh::R];
+#pragma unroll
+        for (int m = 0; m < Sh::R; ++m) v[m] = cmul(sp[to + Sh::NT * m], bz[to + Sh::NT * m]);
+        fft_wg<Sh, +1>(v, lds, tw, t);
+        float *__restrict__ row = plane + int64_t(iz) * nb + kbase;
+#pragma unroll
+        for (int m = 0; m < Sh::R; ++m) {
+            const int n = to + Sh::NT * m;
+            if (n >= h && n < nend) row[n] = cnorm(v[m]);
+        }
+    }
+}
+
+// ------------------------------------------------ harmonic sum and peaks
+struct Thr {
+    float v[5];
+};
+
+// Sums over 2^0 .. 2^levels harmonics with the top harmonic at (iz, k):
+// S_nh = sum_{j=1}^{nh} P[iz_j][k_j], k_j = floor((2 j k + nh) / (2 nh)),
+// iz_j = izc + sgn(d) floor((2 |d| j + nh) / (2 nh)), d = iz - izc.
+// Even j of S_nh are the cells of S_{nh/2}, so each level adds its odd j.
+__device__ __forceinline__ void harm_sums(const float *__restrict__ P, int64_t nb, int izc, int iz,
+                                          int k, int levels, float (&s)[5]) {
+    const int d = iz - izc;
+    const int ad = d < 0 ? -d : d;
+    const int sg = d < 0 ? -1 : 1;
+    float acc = P[int64_t(iz) * nb + k];
+    s[0] = acc;
+    for (int l = 1; l <= levels; ++l) {
+        const int nh = 1 << l;
+        float add = 0.f;
+        for (int j = 1; j < nh; j += 2) {
+            const int kj = (2 * j * k + nh) / (2 * nh);
+            const int izj = izc + sg * ((2 * ad * j + nh) / (2 * nh));
+            add += P[int64_t(izj) * nb + kj];
+        }
+        acc += add;
+        s[l] = acc;
+    }
+}
+
+constexpr int kHsThreads = 256;
+
+__global__ __launch_bounds__(kHsThreads) void k_harmsum(const float *__restrict__ P, int nz, int64_t nb,
+                                                        int izc, int levels, Thr thr,
+                                                        DevCand *__restrict__ cands,
+                                                        uint32_t *__restrict__ count, uint32_t cap) {
+    const int64_t kk = int64_t(blockIdx.x) * kHsThreads + threadIdx.x;
+    const int iz = blockIdx.y;
+    if (kk >= nb) return;
+    const int k = int(kk);
+    float s[5];
+    harm_sums(P, nb, izc, iz, k, levels, s);
+    for (int l = 0; l <= levels; ++l) {
+        if (!(s[l] >= thr.v[l])) continue;
+        bool peak = true;
+        for (int di = -1; di <= 1 && peak; ++di) {
+            const int iz2 = iz + di;
+            if (iz2 < 0 || iz2 >= nz) continue;
+            for (int dk = -1; dk <= 1; ++dk) {
+                if (di == 0 && dk == 0) continue;
+                const int64_t k2 = kk + dk;
+                if (k2 < 0 || k2 >= nb) continue;
+                float s2[5];
+                harm_sums(P, nb, izc, iz2, int(k2), l, s2);
+                const bool earlier = di < 0 || (di == 0 && dk < 0);
+                if (earlier ? !(s[l] > s2[l]) : !(s[l] >= s2[l])) {
+                    peak = false;
+                    break;
+                }
+            }
+        }
+        if (!peak) continue;
+        const uint32_t slot = atomicAdd(count, 1u);
+        if (slot < cap) cands[slot] = DevCand{k, iz, 1 << l, s[l]};
+    }
+}
+
+__global__ void k_zero_u32(uint32_t *__restrict__ p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// ------------------------------------------------------------ dispatch
+
+#define FDAS_SWITCH_LOG2(L, CALL) \
+    switch (L) {                  \
+        case 6: CALL(6); break;   \
+        case 7: CALL(7); break;   \
+        case 8: CALL(8); break;   \
+        case 9: CALL(9); break;   \
+        case 10: CALL(10); break; \
+        case 11: CALL(11); break; \
+        case 12: CALL(12); break; \
+        case 13: CALL(13); break; \
+        default: return hipErrorInvalidValue; \
+    }
+
+}  // namespace
+
+hipError_t launch_dft(int log2n, int dir, int64_t batch, const float2 *in, float2 *out, hipStream_t st) {
+    if (batch <= 0) return hipSuccess;
+    if (batch > 0x7fffffff) return hipErrorInvalidValue;
+#define CALL(L)                                                                                        \
+    if (dir < 0)                                                                                       \
+        hipLaunchKernelGGL((k_dft<L, -1>), dim3(unsigned(batch)), dim3(fft_threads(L)), 0, st, in, out); \
+    else                                                                                               \
+        hipLaunchKernelGGL((k_dft<L, +1>), dim3(unsigned(batch)), dim3(fft_threads(L)), 0, st, in, out);
+    FDAS_SWITCH_LOG2(log2n, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_r2c_packed(const float *x, int64_t nsamp, float2 *Z, float2 *work, hipStream_t st) {
+    const float2 *z = reinterpret_cast<const float2 *>(x);
+    int log2m = 0;
+    while ((int64_t(1) << log2m) < nsamp / 2) ++log2m;
+    if ((int64_t(1) << log2m) != nsamp / 2 || log2m < 6 || log2m > 26) return hipErrorInvalidValue;
+    if (log2m <= 13) {
+#define CALL(L) hipLaunchKernelGGL((k_r2c_small<L>), dim3(1), dim3(fft_threads(L)), 0, st, z, Z);
+        FDAS_SWITCH_LOG2(log2m, CALL)
+#undef CALL
+        return hipGetLastError();
+    }
+    const int l1 = (log2m + 1) / 2, l2 = log2m / 2;
+    const unsigned ncols = 1u << l2, nrows = 1u << l1;
+#define CALL(L) hipLaunchKernelGGL((k_r2c_cols<L>), dim3(ncols), dim3(fft_threads(L)), 0, st, z, work, l2);
+    FDAS_SWITCH_LOG2(l1, CALL)
+#undef CALL
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+#define CALL(L) hipLaunchKernelGGL((k_r2c_rows<L>), dim3(nrows), dim3(fft_threads(L)), 0, st, work, Z, l1);
+    FDAS_SWITCH_LOG2(l2, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_median(const float2 *Z, int64_t nsamp, float2 *X, double *med, int W, hipStream_t st) {
+    const int64_t M = nsamp / 2;
+    if (W < 2 || W > kMaxW || (W & (W - 1))) return hipErrorInvalidValue;
+    const int64_t nblk = (M + W - 1) / W;
+    hipLaunchKernelGGL(k_unpack_median, dim3(unsigned(nblk)), dim3(kMedThreads), 0, st, Z, M, X, med, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_median(const float2 *X, int64_t nb, double *med, int W, hipStream_t st) {
+    if (W < 2 || W > kMaxW || (W & (W - 1))) return hipErrorInvalidValue;
+    const int64_t nblk = (nb + W - 1) / W;
+    hipLaunchKernelGGL(k_median, dim3(unsigned(nblk)), dim3(kMedThreads), 0, st, X, nb, med, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_segfft(const float2 *X, const double *med, int W, int64_t nb, int log2s, int h,
+                         int64_t nseg, float2 *segspec, hipStream_t st) {
+    if (nseg <= 0) return hipSuccess;
+#define CALL(L) \
+    hipLaunchKernelGGL((k_segfft<L>), dim3(unsigned(nseg)), dim3(fft_threads(L)), 0, st, X, med, W, nb, h, segspec);
+    FDAS_SWITCH_LOG2(log2s, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3(unsigned((n + 255) / 256)), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_normalise(const float2 *X, const double *med, int W, int64_t nb, float2 *out, hipStream_t st) {
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_normalise, dim3(unsigned((nb + 255) / 256)), dim3(256), 0, st, X, med, W, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, int tpb, int64_t nb,
+                            int log2s, int h, int64_t nseg, float *plane, hipStream_t st) {
+    if (nseg <= 0 || nz <= 0) return hipSuccess;
+    if (tpb <= 0) return hipErrorInvalidValue;
+    const int64_t nzb = (nz + tpb - 1) / tpb;
+    const int64_t total = nzb * nseg;
+    const int64_t per = (total + kXcds - 1) / kXcds;
+    const int64_t grid = per * kXcds;
+    if (grid > 0x7fffffff) return hipErrorInvalidValue;
+#define CALL(L)                                                                                       \
+    hipLaunchKernelGGL((k_correlate<L>), dim3(unsigned(grid)), dim3(fft_threads(L)), 0, st, segspec, bank, \
+                       nz, tpb, nb, h, nseg, total, per, plane);
+    FDAS_SWITCH_LOG2(log2s, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+hipError_t launch_harmsum(const float *plane, int nz, int64_t nb, int izc, int nharm_max, const float *thr_host,
+                          DevCand *cands, uint32_t *count, uint32_t cap, hipStream_t st) {
+    int levels = 0;
+    while ((1 << levels) < nharm_max) ++levels;
+    if ((1 << levels) != nharm_max || levels > 4) return hipErrorInvalidValue;
+    Thr thr{};
+    for (int l = 0; l <= levels; ++l) thr.v[l] = thr_host[l];
+    const dim3 grid(unsigned((nb + kHsThreads - 1) / kHsThreads), unsigned(nz));
+    hipLaunchKernelGGL(k_harmsum, grid, dim3(kHsThreads), 0, st, plane, nz, nb, izc, levels, thr, cands, count, cap);
+    return hipGetLastError();
+}
+
+}  // namespace fdas

@@ -1,0 +1,59 @@
+// Launchers of the FDAS device kernels (gfx950).  All launches are
+// asynchronous on the given stream and return the hipError_t of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fdas {
+
+// Candidate record written by the harmonic-sum kernel (16 bytes).
+struct DevCand {
+    int32_t k;
+    int32_t iz;
+    int32_t nharm;
+    float power;
+};
+
+// p[0..n) = 0 with a kernel (safe inside captured graphs).
+hipError_t launch_zero_u32(uint32_t *p, int n, hipStream_t st);
+
+// Batched unnormalised complex DFT of length 2^log2n (6..13), dir -1 / +1.
+hipError_t launch_dft(int log2n, int dir, int64_t batch, const float2 *in, float2 *out, hipStream_t st);
+
+// Complex DFT of z[n] = x[2n] + i x[2n+1] (M = N/2 points) into Z, natural
+// order.  work: M float2 scratch (used when M > 8192).
+hipError_t launch_r2c_packed(const float *x, int64_t nsamp, float2 *Z, float2 *work, hipStream_t st);
+
+// Unpack Z into the real-input spectrum X[k], k in [0, M) (X[0] = 0), and the
+// median of |X|^2 over each block of W bins (FP64 out).
+hipError_t launch_unpack_median(const float2 *Z, int64_t nsamp, float2 *X, double *med, int W, hipStream_t st);
+
+// Block medians of |X|^2 of a given spectrum.
+hipError_t launch_median(const float2 *X, int64_t nb, double *med, int W, hipStream_t st);
+
+// Segment spectra: seg s = DFT_S of Xhat[s L - h + n], n in [0, S), where
+// Xhat = X sqrt(ln2 / m(k)) (m interpolated between block medians in FP64;
+// med == nullptr means X is already normalised); zero outside [0, nb).
+hipError_t launch_segfft(const float2 *X, const double *med, int W, int64_t nb, int log2s, int h,
+                         int64_t nseg, float2 *segspec, hipStream_t st);
+
+// Xhat = X sqrt(ln2 / m(k)) into out (inspection; the search fuses it).
+hipError_t launch_normalise(const float2 *X, const double *med, int W, int64_t nb, float2 *out, hipStream_t st);
+
+// Fused correlation: for each segment s and template iz,
+//   y = IDFT_S(segspec[s] * bank[iz]) (unnormalised; bank carries 1/S),
+//   plane[iz][s L + n - h] = |y[n]|^2 for n in [h, S - h), inside [0, nb).
+hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, int tpb, int64_t nb,
+                            int log2s, int h, int64_t nseg, float *plane, hipStream_t st);
+
+// Harmonic sums over 1..nharm_max harmonics, threshold and 3x3 local maxima.
+// thr[i] is the threshold of 2^i harmonics.  Appends to cands (capacity cap)
+// through the counter *count (which must start at 0; it ends holding the true
+// number found).
+hipError_t launch_harmsum(const float *plane, int nz, int64_t nb, int izc, int nharm_max,
+                          const float *thr_host, DevCand *cands, uint32_t *count, uint32_t cap,
+                          hipStream_t st);
+
+}  // namespace fdas

@@ -72,15 +72,22 @@ def add_pulsar(x64: np.ndarray, p: Pulsar) -> None:
     """Add ``p`` in place to the float64 series ``x64``."""
     n = x64.shape[0]
     nb = n // 2
+    keep = [h for h in range(1, p.nharm + 1) if h * p.r + abs(h * p.z) / 2.0 < nb - h]
+    if not keep:
+        return
     u = np.arange(n, dtype=np.float64) / n
     # cycles of the fundamental, reduced mod 1 before scaling to radians so the
     # phase stays accurate for large r
-    for h in range(1, p.nharm + 1):
-        if h * p.r + abs(h * p.z) / 2.0 >= nb - h:
-            continue
-        cyc = h * ((p.r - p.z / 2.0) * u + (p.z / 2.0) * u * u)
-        cyc -= np.floor(cyc)
-        x64 += p.amp * np.cos(h * p.phi0 + 2.0 * np.pi * cyc)
+    cyc = (p.r - p.z / 2.0) * u + (p.z / 2.0) * u * u
+    cyc -= np.floor(cyc)
+    c1 = np.cos(p.phi0 + 2.0 * np.pi * cyc)
+    # cos(h theta) by the Chebyshev recurrence T_h = 2 c1 T_{h-1} - T_{h-2}
+    prev, cur = np.ones(n), c1
+    for h in range(1, max(keep) + 1):
+        if h > 1:
+            prev, cur = cur, 2.0 * c1 * cur - prev
+        if h in keep:
+            x64 += p.amp * cur
 
 
 def make_series(n: int, seed: int, pulsars=(), noise_sigma: float = 1.0) -> Trial:
