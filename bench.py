@@ -160,7 +160,7 @@ def main():
 
     log(f"warmup {args.warmup}")
     for i in range(args.warmup):
-        plan.search(xs[i % len(xs)], cap=1 << 20)
+        plan.search(xs[i % len(xs)])
     torch.cuda.synchronize()
     plan.enable_timing(True)
     lat = []
@@ -169,7 +169,7 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         s0 = time.perf_counter()
-        plan.search(xs[i % len(xs)], cap=1 << 20)
+        plan.search(xs[i % len(xs)])
         lat.append(time.perf_counter() - s0)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -204,12 +204,12 @@ def main():
     if not args.plain_only and args.batch > 0:
         log(f"batched: {args.batch} trials per launch")
         bx = [xs[i % len(xs)] for i in range(args.batch)]
-        plan.search_batch(bx, caps=[1 << 16] * len(bx))
+        plan.search_batch(bx, caps=[1 << 22] * len(bx))
         torch.cuda.synchronize()
         reps = 3
         tb0 = time.perf_counter()
         for _ in range(reps):
-            plan.search_batch(bx, caps=[1 << 16] * len(bx))
+            plan.search_batch(bx, caps=[1 << 22] * len(bx))
         torch.cuda.synchronize()
         tb = time.perf_counter() - tb0
         out["batched"] = {"value": round(reps * len(bx) / tb, 3), "unit": "DM trials/s",

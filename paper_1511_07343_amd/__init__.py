@@ -124,7 +124,7 @@ def _stream_handle(stream=None):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=1 << 20, templates_per_block=0):
+def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=0, templates_per_block=0):
     o = _Opts()
     load().fdas_default_opts(ctypes.byref(o))
     o.sigma = float(sigma)
@@ -138,6 +138,22 @@ def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=1 << 20, te
 def _cands_to_numpy(buf, n: int) -> np.ndarray:
     return np.frombuffer(ctypes.string_at(ctypes.addressof(buf), n * 40), dtype=CAND_DTYPE).copy() \
         if n > 0 else np.zeros(0, dtype=CAND_DTYPE)
+
+
+class _CandBuffer:
+    """Reusable uninitialised host buffer of candidate records."""
+
+    def __init__(self):
+        self.arr = np.empty(0, dtype=CAND_DTYPE)
+
+    def get(self, n: int) -> np.ndarray:
+        if self.arr.shape[0] < n:
+            self.arr = np.empty(n, dtype=CAND_DTYPE)
+        return self.arr
+
+    @staticmethod
+    def ptr(a: np.ndarray):
+        return ctypes.cast(ctypes.c_void_p(a.ctypes.data), ctypes.POINTER(_Cand))
 
 
 def threshold(sigma: float, nharm: int) -> float:
@@ -210,6 +226,7 @@ class Plan:
         self.bank = bank
         self.nsamp, self.seg = int(nsamp), int(seg)
         self.opts = o
+        self._buf = _CandBuffer()
 
     @property
     def nbins(self) -> int:
@@ -219,31 +236,31 @@ class Plan:
     def device_bytes(self) -> int:
         return load().fdas_plan_device_bytes(self._h)
 
-    def search(self, inp, kind: int = IN_SERIES, plane=None, cap: int = 65536, stream=None,
+    def search(self, inp, kind: int = IN_SERIES, plane=None, cap: int = 1 << 22, stream=None,
                allow_overflow: bool = False):
         """Run the hot path on a device tensor; returns (candidates, n_found)."""
-        buf = (_Cand * max(cap, 1))()
+        buf = self._buf.get(max(cap, 1))
         n = ctypes.c_int64()
         st = load().fdas_search(self._h, kind, ctypes.c_void_p(inp.data_ptr()),
                                 ctypes.c_void_p(plane.data_ptr() if plane is not None else 0),
-                                buf, cap, ctypes.byref(n), _stream_handle(stream))
+                                _CandBuffer.ptr(buf), cap, ctypes.byref(n), _stream_handle(stream))
         _check(st, allow=(-4,) if allow_overflow else ())
-        return _cands_to_numpy(buf, min(n.value, cap)), n.value
+        return buf[:min(n.value, cap)].copy(), n.value
 
     def search_batch(self, series: Sequence, caps: Optional[Sequence[int]] = None, stream=None):
         """Several device float32 series; returns a list of candidate arrays."""
         k = len(series)
-        caps = list(caps) if caps is not None else [65536] * k
+        caps = list(caps) if caps is not None else [1 << 20] * k
         ptrs = (ctypes.c_void_p * k)(*[s.data_ptr() for s in series])
         ns = (ctypes.c_int64 * k)(*[int(s.numel()) for s in series])
         cp = (ctypes.c_int64 * k)(*caps)
         nc = (ctypes.c_int64 * k)()
-        buf = (_Cand * max(1, sum(caps)))()
-        _check(load().fdas_search_batch(self._h, k, ptrs, ns, buf, cp, nc, _stream_handle(stream)))
+        buf = self._buf.get(max(1, sum(caps)))
+        _check(load().fdas_search_batch(self._h, k, ptrs, ns, _CandBuffer.ptr(buf), cp, nc,
+                                        _stream_handle(stream)))
         out, off = [], 0
-        allc = _cands_to_numpy(buf, sum(caps))
         for i in range(k):
-            out.append(allc[off: off + min(nc[i], caps[i])].copy())
+            out.append(buf[off: off + min(nc[i], caps[i])].copy())
             off += caps[i]
         return out
 
@@ -287,23 +304,24 @@ class Server:
                                          int(hbm_budget), int(max_slots), ctypes.byref(h)))
         self._h = h
         self.bank = bank
+        self._buf = _CandBuffer()
 
     def submit(self, series: np.ndarray, tag: int):
         x = np.ascontiguousarray(series, dtype=np.float32)
         _check(load().fdas_submit(self._h, ctypes.c_void_p(x.ctypes.data), x.shape[0], int(tag)))
 
-    def poll(self, timeout_ms: int = -1, cap: int = 65536):
+    def poll(self, timeout_ms: int = -1, cap: int = 1 << 22):
         """Returns (tag, candidates, n_found, latency_s), or None on timeout."""
         tag = ctypes.c_uint64()
         n = ctypes.c_int64()
         lat = ctypes.c_double()
-        buf = (_Cand * max(cap, 1))()
-        st = load().fdas_poll(self._h, ctypes.byref(tag), buf, cap, ctypes.byref(n), ctypes.byref(lat),
-                              int(timeout_ms))
+        buf = self._buf.get(max(cap, 1))
+        st = load().fdas_poll(self._h, ctypes.byref(tag), _CandBuffer.ptr(buf), cap, ctypes.byref(n),
+                              ctypes.byref(lat), int(timeout_ms))
         if st == -6:
             return None
         _check(st)
-        return tag.value, _cands_to_numpy(buf, min(n.value, cap)), n.value, lat.value
+        return tag.value, buf[:min(n.value, cap)].copy(), n.value, lat.value
 
     @property
     def outstanding(self) -> int:

@@ -82,20 +82,10 @@ extern "C" fdas_status fdas_search_batch(fdas_plan_t *plan, int32_t n, const flo
     // records and convert them.
     auto finish = [&](int32_t j) -> fdas_status {
         const int slot = j % 2;
-        Workspace &ws = plan->ws[slot];
         hipError_t ee = hipEventSynchronize(plan->events[slot]);
         if (ee != hipSuccess) return hip_fail(plan, ee, "batch trial");
-        const uint32_t found = *ws.h_count;
-        const int64_t got = std::min<int64_t>(found, plan->opts.cand_capacity);
-        if (got > 0) {
-            ee = hipMemcpyAsync(ws.h_cands, ws.cands, size_t(got) * sizeof(DevCand), hipMemcpyDeviceToHost,
-                                plan->aux[slot]);
-            if (ee != hipSuccess) return hip_fail(plan, ee, "copy candidates");
-            ee = hipStreamSynchronize(plan->aux[slot]);
-            if (ee != hipSuccess) return hip_fail(plan, ee, "copy candidates");
-        }
-        fdas_status r = finish_candidates(plan, found, ws.h_cands, cands_host + offset[size_t(j)], cap[j],
-                                          &ncands[j]);
+        fdas_status r = copy_candidates(plan, plan->ws[slot], cands_host + offset[size_t(j)], cap[j], &ncands[j],
+                                        plan->aux[slot]);
         if (r == FDAS_E_OVERFLOW) {
             overflow = true;
             r = FDAS_OK;

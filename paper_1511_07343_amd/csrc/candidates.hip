@@ -1,0 +1,244 @@
+// Candidate finishing on the device: order the harmonic-sum kernel's
+// (unordered) records by (nharm, k, iz) with an LSD radix sort, then write
+// the public records with r, z and the FP64 single-trial significance.
+// The record count stays on the device: every kernel reads it and clamps it
+// to the buffer capacity, so nothing waits for the host in between.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/fdas.h"
+#include "kernels.hpp"
+
+namespace fdas {
+
+namespace {
+
+constexpr int RS_BLOCKS = 256;   // workgroups of the histogram and scatter passes
+constexpr int RS_THREADS = 256;  // four waves
+constexpr int RS_DIGITS = 256;   // 8-bit digits
+
+__device__ __forceinline__ uint32_t clamp_count(const uint32_t *count, uint32_t cap) {
+    const uint32_t c = *count;
+    return c < cap ? c : cap;
+}
+
+// key = level << 40 | k << 14 | iz, level = log2(nharm): ascending keys are
+// ascending (nharm, k, iz).
+__global__ __launch_bounds__(256) void k_cand_keys(const DevCand *__restrict__ dc, const uint32_t *__restrict__ count,
+                                                   uint32_t cap, uint64_t *__restrict__ keys,
+                                                   uint32_t *__restrict__ vals) {
+    const uint32_t n = clamp_count(count, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const DevCand c = dc[i];
+        const uint64_t level = uint64_t(31 - __clz(c.nharm));
+        keys[i] = (level << 40) | (uint64_t(uint32_t(c.k)) << 14) | uint64_t(uint32_t(c.iz));
+        vals[i] = i;
+    }
+}
+
+__device__ __forceinline__ void block_range(uint32_t n, uint32_t &beg, uint32_t &end) {
+    const uint32_t chunk = (n + RS_BLOCKS - 1) / RS_BLOCKS;
+    beg = min(n, blockIdx.x * chunk);
+    end = min(n, beg + chunk);
+}
+
+// Per-block digit counts, digit-major: hist[d * RS_BLOCKS + block].
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *__restrict__ keys,
+                                                        const uint32_t *__restrict__ count, uint32_t cap,
+                                                        int shift, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t lh[RS_DIGITS];
+    const int t = threadIdx.x;
+    lh[t] = 0;
+    __syncthreads();
+    uint32_t beg, end;
+    block_range(clamp_count(count, cap), beg, end);
+    for (uint32_t i = beg + t; i < end; i += RS_THREADS) atomicAdd(&lh[(keys[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    hist[t * RS_BLOCKS + blockIdx.x] = lh[t];
+}
+
+// Exclusive scan of the RS_DIGITS * RS_BLOCKS counts (one workgroup).
+constexpr int SCAN_THREADS = 1024;
+constexpr int SCAN_PER = RS_DIGITS * RS_BLOCKS / SCAN_THREADS;
+__global__ __launch_bounds__(SCAN_THREADS) void k_rs_scan(uint32_t *__restrict__ hist) {
+    __shared__ uint32_t part[SCAN_THREADS];
+    const int t = threadIdx.x;
+    uint32_t loc[SCAN_PER];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_PER; ++i) {
+        loc[i] = hist[t * SCAN_PER + i];
+        sum += loc[i];
+    }
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < SCAN_THREADS; off <<= 1) {  // Hillis-Steele inclusive scan
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+#pragma unroll
+    for (int i = 0; i < SCAN_PER; ++i) {
+        hist[t * SCAN_PER + i] = run;
+        run += loc[i];
+    }
+}
+
+// Stable scatter of one 8-bit digit.  Each block re-walks its range in tiles
+// of 256 (one element per thread, element order = wave-major lane order); a
+// lane's rank among same-digit lanes of its wave comes from 8 ballots, wave
+// offsets from LDS counts, and a running per-digit offset carries across
+// tiles.
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *__restrict__ kin,
+                                                           const uint32_t *__restrict__ vin,
+                                                           const uint32_t *__restrict__ count, uint32_t cap,
+                                                           int shift, const uint32_t *__restrict__ hist,
+                                                           uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+    __shared__ uint32_t base[RS_DIGITS];
+    __shared__ uint32_t cnt[RS_THREADS / 64][RS_DIGITS];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    base[t] = hist[t * RS_BLOCKS + blockIdx.x];
+    uint32_t beg, end;
+    block_range(clamp_count(count, cap), beg, end);
+    const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
+    for (uint32_t tile = beg; tile < end; tile += RS_THREADS) {
+#pragma unroll
+        for (int ww = 0; ww < RS_THREADS / 64; ++ww) cnt[ww][t] = 0;
+        __syncthreads();
+        const uint32_t i = tile + t;
+        const bool valid = i < end;
+        uint64_t key = 0;
+        uint32_t val = 0, d = 0;
+        if (valid) {
+            key = kin[i];
+            val = vin[i];
+            d = uint32_t(key >> shift) & 255u;
+        }
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(valid && bit);
+            peers &= bit ? m : ~m;
+        }
+        const uint32_t rank = __popcll(peers & lt_mask);
+        if (valid && rank == 0) cnt[w][d] = __popcll(peers);
+        __syncthreads();
+        // thread t owns digit t: offsets of each wave within the tile
+        uint32_t o = 0;
+#pragma unroll
+        for (int ww = 0; ww < RS_THREADS / 64; ++ww) {
+            const uint32_t c = cnt[ww][t];
+            cnt[ww][t] = o;
+            o += c;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = base[d] + cnt[w][d] + rank;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        base[t] += o;
+    }
+}
+
+// ------------------------------------------------- significance (FP64)
+__device__ double log_gamma_survival_d(int n, double s) {
+    if (s <= 0.0) return 0.0;
+    const double ls = log(s);
+    double mx = -INFINITY, lf = 0.0;
+    for (int i = 0; i < n; ++i) {  // log(i!) accumulated exactly enough for i <= 16
+        if (i > 0) lf += log(double(i));
+        mx = fmax(mx, double(i) * ls - lf);
+    }
+    double acc = 0.0;
+    lf = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (i > 0) lf += log(double(i));
+        acc += exp(double(i) * ls - lf - mx);
+    }
+    return -s + mx + log(acc);
+}
+
+__device__ double log_normal_tail_d(double sg) {
+    if (sg < 30.0) return log(0.5 * erfc(sg * 0.70710678118654752440));
+    const double s2 = 1.0 / (sg * sg);
+    const double series = 1.0 - s2 + 3.0 * s2 * s2 - 15.0 * s2 * s2 * s2 + 105.0 * s2 * s2 * s2 * s2;
+    return -0.5 * sg * sg - log(sg) - 0.91893853320467274178 + log(series);
+}
+
+// sigma with Phi_c(sigma) = Q(n, power), by bisection.
+__device__ double significance_d(double power, int n) {
+    const double target = log_gamma_survival_d(n, power);
+    double lo = -40.0, hi = 40.0;
+    if (log_normal_tail_d(lo) < target) return lo;
+    while (log_normal_tail_d(hi) > target && hi < 1e9) hi *= 2.0;
+    for (int it = 0; it < 200 && hi - lo > 1e-12 * fmax(1.0, fabs(hi)); ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (log_normal_tail_d(mid) > target) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+__global__ __launch_bounds__(256) void k_cand_finalize(const DevCand *__restrict__ dc,
+                                                       const uint32_t *__restrict__ order,
+                                                       const uint32_t *__restrict__ count, uint32_t cap,
+                                                       double zmax, double dz, fdas_cand *__restrict__ out) {
+    const uint32_t n = clamp_count(count, cap);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const DevCand c = dc[order[i]];
+        fdas_cand o;
+        o.k = c.k;
+        o.iz = c.iz;
+        o.nharm = c.nharm;
+        o.r = double(c.k) / double(c.nharm);
+        o.z = (-zmax + double(c.iz) * dz) / double(c.nharm);
+        o.power = c.power;
+        o.sigma = float(significance_d(double(c.power), c.nharm));
+        out[i] = o;
+    }
+}
+
+}  // namespace
+
+size_t cand_sort_scratch_bytes(uint32_t cap) {
+    return size_t(cap) * (2 * sizeof(uint64_t) + 2 * sizeof(uint32_t)) + size_t(RS_DIGITS) * RS_BLOCKS * 4;
+}
+
+hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch,
+                                    double zmax, double dz, fdas_cand *out, hipStream_t st) {
+    if (cap == 0) return hipSuccess;
+    uint64_t *k0 = static_cast<uint64_t *>(scratch);
+    uint64_t *k1 = k0 + cap;
+    uint32_t *v0 = reinterpret_cast<uint32_t *>(k1 + cap);
+    uint32_t *v1 = v0 + cap;
+    uint32_t *hist = v1 + cap;
+    const uint64_t blocks = (uint64_t(cap) + 255) / 256;
+    const unsigned grid = unsigned(blocks < 1024 ? blocks : 1024);
+    hipLaunchKernelGGL(k_cand_keys, dim3(grid), dim3(256), 0, st, dc, count, cap, k0, v0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // 43 key bits (3 level, 26 k, 14 iz): six 8-bit passes, ending in k0/v0
+    for (int shift = 0; shift < 48; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(RS_BLOCKS), dim3(RS_THREADS), 0, st, k0, count, cap, shift, hist);
+        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(SCAN_THREADS), 0, st, hist);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(RS_BLOCKS), dim3(RS_THREADS), 0, st, k0, v0, count, cap, shift, hist, k1,
+                           v1);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        uint64_t *tk = k0;
+        k0 = k1;
+        k1 = tk;
+        uint32_t *tv = v0;
+        v0 = v1;
+        v1 = tv;
+    }
+    hipLaunchKernelGGL(k_cand_finalize, dim3(grid), dim3(256), 0, st, dc, v0, count, cap, zmax, dz, out);
+    return hipGetLastError();
+}
+
+}  // namespace fdas

@@ -34,10 +34,11 @@ struct Workspace {
     double *med = nullptr;   // block medians of |X|^2
     float2 *seg = nullptr;   // segment spectra, nseg x S
     float *plane = nullptr;  // f-fdot plane, nz x nb
-    DevCand *cands = nullptr;
-    uint32_t *count = nullptr;
-    DevCand *h_cands = nullptr;  // pinned host copies
-    uint32_t *h_count = nullptr;
+    DevCand *cands = nullptr;     // unordered records from the harmonic-sum kernel
+    uint32_t *count = nullptr;    // their count (may exceed the capacity)
+    void *sort = nullptr;         // radix-sort scratch
+    fdas_cand *final = nullptr;   // sorted public records
+    uint32_t *h_count = nullptr;  // pinned host copy of the count
 };
 
 }  // namespace fdas
@@ -47,6 +48,7 @@ struct fdas_plan_s {
     double zmax = 0.0, dz = 1.0;
     int32_t nz = 0, h = 0, izc = 0, S = 0, log2s = 0, W = 1024, tpb = 13;
     int64_t nsamp = 0;
+    uint32_t cand_cap = 0;  // device candidate capacity (records)
     int device = 0;
     double thr_d[5] = {};
     float thr_f[5] = {};
@@ -75,14 +77,17 @@ fdas_status validate_opts(const fdas_opts &o);
 fdas_status check_nsamp(int64_t nsamp, int32_t seg, int32_t h);
 Geometry make_geometry(int64_t nsamp, int32_t S, int32_t h, int32_t W);
 int64_t series_bytes(const Geometry &g, int32_t S, int32_t nz);
+int64_t candidate_bytes(uint32_t cap);
 fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp);
 void destroy_workspace(Workspace &ws);
 fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &g, int32_t in_kind,
                            const void *in_dev, float *plane, DevCand *dcands, uint32_t *dcount, hipStream_t st,
                            bool timed = false);
 fdas_status accumulate_timing(fdas_plan_s *p);
-fdas_status finish_candidates(const fdas_plan_s *p, uint32_t found, const DevCand *hc, fdas_cand *out,
-                              int64_t cap, int64_t *ncands);
+// Copy a finished search's sorted candidates (count already in *ws.h_count
+// after the stream reached it) into out[0..cap); sets *ncands to the true count.
+fdas_status copy_candidates(const fdas_plan_s *p, const Workspace &ws, fdas_cand *out, int64_t cap,
+                            int64_t *ncands, hipStream_t st);
 // Plan without work buffers: options, thresholds, bank in the segment domain.
 fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, const fdas_opts *opts,
                            fdas_plan_s **out);

@@ -47,8 +47,8 @@ fdas_status validate_opts(const fdas_opts &o) {
         set_error("opts.median_window must be a power of two in [32, 8192]");
         return FDAS_E_INVAL;
     }
-    if (o.cand_capacity < 1 || o.cand_capacity > (int64_t(1) << 28)) {
-        set_error("opts.cand_capacity must be in [1, 2^28]");
+    if (o.cand_capacity < 0 || o.cand_capacity > (int64_t(1) << 28)) {
+        set_error("opts.cand_capacity must be in [0, 2^28] (0 = automatic)");
         return FDAS_E_INVAL;
     }
     if (o.templates_per_block < 0 || o.templates_per_block > 4096) {
@@ -84,6 +84,10 @@ Geometry make_geometry(int64_t nsamp, int32_t S, int32_t h, int32_t W) {
 int64_t series_bytes(const Geometry &g, int32_t S, int32_t nz) {
     const int64_t M = g.nb;
     return 3 * M * 8 + g.nblk * 8 + g.nseg * int64_t(S) * 8 + int64_t(nz) * g.nb * 4;
+}
+
+int64_t candidate_bytes(uint32_t cap) {
+    return int64_t(cap) * int64_t(sizeof(DevCand) + sizeof(fdas_cand)) + int64_t(cand_sort_scratch_bytes(cap)) + 64;
 }
 
 // Run the whole per-series path on `st`, writing the plane into `plane` and
@@ -124,9 +128,10 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
     if ((e = mark(4)) != hipSuccess) return hip_fail(p, e, "timing event");
     e = launch_zero_u32(dcount, 1, st);
     if (e != hipSuccess) return hip_fail(p, e, "zero counter");
-    e = launch_harmsum(plane, p->nz, g.nb, p->izc, p->opts.nharm_max, p->thr_f, dcands, dcount,
-                       uint32_t(p->opts.cand_capacity), st);
+    e = launch_harmsum(plane, p->nz, g.nb, p->izc, p->opts.nharm_max, p->thr_f, dcands, dcount, p->cand_cap, st);
     if (e != hipSuccess) return hip_fail(p, e, "harmonic sum");
+    e = launch_finish_candidates(dcands, dcount, p->cand_cap, ws.sort, p->zmax, p->dz, ws.final, st);
+    if (e != hipSuccess) return hip_fail(p, e, "candidate sort");
     if ((e = mark(5)) != hipSuccess) return hip_fail(p, e, "timing event");
     p->last_X = X;
     p->last_med = med;
@@ -146,30 +151,17 @@ fdas_status accumulate_timing(fdas_plan_s *p) {
     return FDAS_OK;
 }
 
-// Turn device records into sorted fdas_cand entries.
-fdas_status finish_candidates(const fdas_plan_s *p, uint32_t found, const DevCand *hc, fdas_cand *out,
-                              int64_t cap, int64_t *ncands) {
-    const int64_t got = std::min<int64_t>(found, p->opts.cand_capacity);
-    std::vector<DevCand> v(hc, hc + got);
-    std::sort(v.begin(), v.end(), [](const DevCand &a, const DevCand &b) {
-        if (a.nharm != b.nharm) return a.nharm < b.nharm;
-        if (a.k != b.k) return a.k < b.k;
-        return a.iz < b.iz;
-    });
-    const int64_t nout = std::min<int64_t>(got, cap);
-    for (int64_t i = 0; i < nout; ++i) {
-        const DevCand &c = v[size_t(i)];
-        fdas_cand &o = out[i];
-        o.k = c.k;
-        o.iz = c.iz;
-        o.nharm = c.nharm;
-        o.r = double(c.k) / double(c.nharm);
-        o.z = (-p->zmax + double(c.iz) * p->dz) / double(c.nharm);
-        o.power = c.power;
-        o.sigma = float(significance(double(c.power), c.nharm));
+fdas_status copy_candidates(const fdas_plan_s *p, const Workspace &ws, fdas_cand *out, int64_t cap,
+                            int64_t *ncands, hipStream_t st) {
+    const uint32_t found = *ws.h_count;
+    const int64_t n = std::min<int64_t>(std::min<int64_t>(found, p->cand_cap), cap);
+    if (n > 0) {
+        hipError_t e = hipMemcpyAsync(out, ws.final, size_t(n) * sizeof(fdas_cand), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(const_cast<fdas_plan_s *>(p), e, "copy candidates");
     }
     if (ncands) *ncands = found;
-    if (int64_t(found) > cap || int64_t(found) > p->opts.cand_capacity) {
+    if (int64_t(found) > cap || found > p->cand_cap) {
         set_error("candidate capacity exceeded");
         return FDAS_E_OVERFLOW;
     }
@@ -185,7 +177,8 @@ static void free_workspace(Workspace &ws) {
     if (ws.plane) (void)hipFree(ws.plane);
     if (ws.cands) (void)hipFree(ws.cands);
     if (ws.count) (void)hipFree(ws.count);
-    if (ws.h_cands) (void)hipHostFree(ws.h_cands);
+    if (ws.sort) (void)hipFree(ws.sort);
+    if (ws.final) (void)hipFree(ws.final);
     if (ws.h_count) (void)hipHostFree(ws.h_count);
     ws = Workspace{};
 }
@@ -207,16 +200,11 @@ fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp) {
     FDAS_ALLOC(ws.med, g.nblk * 8);
     FDAS_ALLOC(ws.seg, g.nseg * int64_t(p->S) * 8);
     FDAS_ALLOC(ws.plane, int64_t(p->nz) * g.nb * 4);
-    FDAS_ALLOC(ws.cands, p->opts.cand_capacity * int64_t(sizeof(DevCand)));
+    FDAS_ALLOC(ws.cands, int64_t(p->cand_cap) * int64_t(sizeof(DevCand)));
     FDAS_ALLOC(ws.count, 64);
+    FDAS_ALLOC(ws.sort, cand_sort_scratch_bytes(p->cand_cap));
+    FDAS_ALLOC(ws.final, int64_t(p->cand_cap) * int64_t(sizeof(fdas_cand)));
 #undef FDAS_ALLOC
-    e = hipHostMalloc(reinterpret_cast<void **>(&ws.h_cands), size_t(p->opts.cand_capacity) * sizeof(DevCand),
-                      hipHostMallocDefault);
-    if (e != hipSuccess) {
-        free_workspace(ws);
-        set_error("hipHostMalloc candidates");
-        return FDAS_E_NOMEM;
-    }
     e = hipHostMalloc(reinterpret_cast<void **>(&ws.h_count), 64, hipHostMallocDefault);
     if (e != hipSuccess) {
         free_workspace(ws);
@@ -236,17 +224,8 @@ fdas_status collect(fdas_plan_s *p, Workspace &ws, fdas_cand *out, int64_t cap, 
     if (e != hipSuccess) return hip_fail(p, e, "copy candidate count");
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(p, e, "search");
-    const uint32_t found = *ws.h_count;
-    const int64_t got = std::min<int64_t>(found, p->opts.cand_capacity);
-    if (got > 0) {
-        e = hipMemcpyAsync(ws.h_cands, ws.cands, size_t(got) * sizeof(DevCand), hipMemcpyDeviceToHost, st);
-        if (e != hipSuccess) return hip_fail(p, e, "copy candidates");
-        e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(p, e, "copy candidates");
-    }
-    return finish_candidates(p, found, ws.h_cands, out, cap, ncands);
+    return copy_candidates(p, ws, out, cap, ncands, st);
 }
-
 
 fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, const fdas_opts *opts,
                            fdas_plan_s **out) {
@@ -285,6 +264,10 @@ fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, 
     p->W = o.median_window;
     p->nsamp = nsamp;
     p->tpb = o.templates_per_block > 0 ? o.templates_per_block : default_tpb(bank->nz);
+    p->cand_cap = uint32_t(o.cand_capacity > 0
+                               ? o.cand_capacity
+                               : std::min<int64_t>(int64_t(1) << 22,
+                                                   std::max<int64_t>(int64_t(1) << 16, int64_t(bank->nz) * (nsamp / 2) / 256)));
     int levels = 0;
     while ((1 << levels) < o.nharm_max) ++levels;
     for (int l = 0; l < 5; ++l) {
@@ -339,7 +322,7 @@ void fdas_default_opts(fdas_opts *opts) {
     opts->sigma = 6.0;
     opts->nharm_max = 16;
     opts->median_window = 1024;
-    opts->cand_capacity = int64_t(1) << 20;
+    opts->cand_capacity = 0;
     opts->templates_per_block = 0;
 }
 
@@ -440,7 +423,9 @@ int64_t fdas_plan_device_bytes(const fdas_plan_t *plan) {
     if (!plan) return 0;
     int64_t b = int64_t(plan->nz) * plan->S * 8;
     for (const Workspace &ws : plan->ws)
-        if (ws.nsamp) b += series_bytes(make_geometry(ws.nsamp, plan->S, plan->h, plan->W), plan->S, plan->nz);
+        if (ws.nsamp)
+            b += series_bytes(make_geometry(ws.nsamp, plan->S, plan->h, plan->W), plan->S, plan->nz) +
+                 candidate_bytes(plan->cand_cap);
     return b;
 }
 

@@ -362,6 +362,133 @@ __global__ __launch_bounds__(kHsThreads) void k_harmsum(const float *__restrict_
     }
 }
 
+// Harmonic sums, second form.  A wave owns 8 columns per lane,
+// k = k0 + lane + 64 i (i < 8), and walks HS_TZ consecutive rows.  Every term
+// of every level is a fraction j/16 of the top harmonic (j = 1..16):
+//   column c_j(k) = floor((j k + 8) / 16),  row r_j(iz) = izc + sgn(d) floor((|d| j + 8) / 16),
+// and since 64 i j / 16 = 4 j i, c_j(k0 + lane + 64 i) = c_j(k0 + lane) + 4 j i:
+// each fraction needs one base address per lane and 8 loads at compile-time
+// offsets.  The 8 values of fraction j are kept in registers and reloaded
+// only when r_j changes between consecutive rows (wave-uniform test).
+constexpr int HS_C = 8;
+constexpr int HS_TZ = 16;
+constexpr int HS_WAVES = 4;
+
+// S_1, S_2, ..., S_2^LEVELS from the 16 fraction values v[j] (v[0] unused),
+// in one fixed order shared by the fast path and the neighbour checks.
+template <int LEVELS>
+__device__ __forceinline__ void nested_sums(const float (&v)[17], float (&s)[5]) {
+    s[0] = v[16];
+    if constexpr (LEVELS >= 1) s[1] = s[0] + v[8];
+    if constexpr (LEVELS >= 2) s[2] = s[1] + (v[4] + v[12]);
+    if constexpr (LEVELS >= 3) s[3] = s[2] + ((v[2] + v[6]) + (v[10] + v[14]));
+    if constexpr (LEVELS >= 4) s[4] = s[3] + (((v[1] + v[3]) + (v[5] + v[7])) + ((v[9] + v[11]) + (v[13] + v[15])));
+}
+
+template <int LEVELS>
+__device__ __forceinline__ constexpr bool frac_used(int j) {
+    // level l uses the odd multiples of 16 / 2^l
+    return (j % (16 >> LEVELS)) == 0;
+}
+
+__device__ __forceinline__ int frac_row(int izc, int d, int j) {
+    const int ad = d < 0 ? -d : d;
+    const int off = (ad * j + 8) >> 4;
+    return d < 0 ? izc - off : izc + off;
+}
+
+// All levels at one cell, loading its terms directly (neighbour checks).
+template <int LEVELS>
+__device__ __forceinline__ void cell_sums2(const float *__restrict__ P, int64_t nb, int izc, int iz, int k,
+                                           float (&s)[5]) {
+    float v[17];
+    const int d = iz - izc;
+    static_for<1, 17>([&](auto jc) {
+        constexpr int j = decltype(jc)::value;
+        if constexpr (frac_used<LEVELS>(j)) v[j] = P[int64_t(frac_row(izc, d, j)) * nb + ((j * k + 8) >> 4)];
+        else v[j] = 0.f;
+    });
+    nested_sums<LEVELS>(v, s);
+}
+
+template <int LEVELS>
+__global__ __launch_bounds__(64 * HS_WAVES) void k_harmsum2(const float *__restrict__ P, int nz, int64_t nb,
+                                                            int izc, Thr thr, DevCand *__restrict__ cands,
+                                                            uint32_t *__restrict__ count, uint32_t cap) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t k0 = (int64_t(blockIdx.x) * HS_WAVES + wave) * (64 * HS_C);
+    if (k0 >= nb) return;
+    const int iz0 = blockIdx.y * HS_TZ;
+    const int iz1 = min(nz, iz0 + HS_TZ);
+    const int kl = int(k0) + lane;
+    float val[17][HS_C];
+    int rowc[17];
+#pragma unroll
+    for (int j = 0; j < 17; ++j) rowc[j] = -1;
+    for (int iz = iz0; iz < iz1; ++iz) {
+        const int d = iz - izc;
+        static_for<1, 17>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            if constexpr (frac_used<LEVELS>(j)) {
+                const int row = frac_row(izc, d, j);
+                if (row != rowc[j]) {
+                    rowc[j] = row;
+                    const float *__restrict__ src = P + int64_t(row) * nb + ((j * kl + 8) >> 4);
+#pragma unroll
+                    for (int i = 0; i < HS_C; ++i)
+                        val[j][i] = (kl + 64 * i < nb) ? src[4 * j * i] : 0.f;
+                }
+            }
+        });
+        // fast path: which (cell, level) pairs reach their threshold
+        uint64_t hits = 0;
+#pragma unroll
+        for (int i = 0; i < HS_C; ++i) {
+            float v[17];
+            v[0] = 0.f;
+#pragma unroll
+            for (int j = 1; j < 17; ++j) v[j] = val[j][i];
+            float s[5];
+            nested_sums<LEVELS>(v, s);
+#pragma unroll
+            for (int l = 0; l <= LEVELS; ++l)
+                if (s[l] >= thr.v[l]) hits |= uint64_t(1) << (5 * i + l);
+        }
+        // rare: check the 3x3 neighbourhood of each hit (sums recomputed from
+        // the same loads in the same order, so they equal the fast path's)
+        while (hits) {
+            const int b = __ffsll((long long)hits) - 1;
+            hits &= hits - 1;
+            const int i = b / 5, l = b % 5;
+            const int k = kl + 64 * i;
+            if (int64_t(k) >= nb) continue;
+            float s[5];
+            cell_sums2<LEVELS>(P, nb, izc, iz, k, s);
+            bool peak = true;
+            for (int di = -1; di <= 1 && peak; ++di) {
+                const int iz2 = iz + di;
+                if (iz2 < 0 || iz2 >= nz) continue;
+                for (int dk = -1; dk <= 1; ++dk) {
+                    if (di == 0 && dk == 0) continue;
+                    const int k2 = k + dk;
+                    if (k2 < 0 || int64_t(k2) >= nb) continue;
+                    float s2[5];
+                    cell_sums2<LEVELS>(P, nb, izc, iz2, k2, s2);
+                    const bool earlier = di < 0 || (di == 0 && dk < 0);
+                    if (earlier ? !(s[l] > s2[l]) : !(s[l] >= s2[l])) {
+                        peak = false;
+                        break;
+                    }
+                }
+            }
+            if (!peak) continue;
+            const uint32_t slot = atomicAdd(count, 1u);
+            if (slot < cap) cands[slot] = DevCand{k, iz, 1 << l, s[l]};
+        }
+    }
+}
+
 __global__ void k_zero_u32(uint32_t *__restrict__ p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
@@ -480,10 +607,21 @@ hipError_t launch_harmsum(const float *plane, int nz, int64_t nb, int izc, int n
     int levels = 0;
     while ((1 << levels) < nharm_max) ++levels;
     if ((1 << levels) != nharm_max || levels > 4) return hipErrorInvalidValue;
+    if (nb > (int64_t(1) << 26)) return hipErrorInvalidValue;
     Thr thr{};
     for (int l = 0; l <= levels; ++l) thr.v[l] = thr_host[l];
-    const dim3 grid(unsigned((nb + kHsThreads - 1) / kHsThreads), unsigned(nz));
-    hipLaunchKernelGGL(k_harmsum, grid, dim3(kHsThreads), 0, st, plane, nz, nb, izc, levels, thr, cands, count, cap);
+    const int64_t cols = 64 * HS_C * HS_WAVES;
+    const dim3 grid(unsigned((nb + cols - 1) / cols), unsigned((nz + HS_TZ - 1) / HS_TZ));
+#define CALL(L) \
+    hipLaunchKernelGGL((k_harmsum2<L>), grid, dim3(64 * HS_WAVES), 0, st, plane, nz, nb, izc, thr, cands, count, cap);
+    switch (levels) {
+        case 0: CALL(0); break;
+        case 1: CALL(1); break;
+        case 2: CALL(2); break;
+        case 3: CALL(3); break;
+        default: CALL(4); break;
+    }
+#undef CALL
     return hipGetLastError();
 }
 

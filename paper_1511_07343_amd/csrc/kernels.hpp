@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "../../include/fdas.h"
+
 namespace fdas {
 
 // Candidate record written by the harmonic-sum kernel (16 bytes).
@@ -55,5 +57,12 @@ hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, i
 hipError_t launch_harmsum(const float *plane, int nz, int64_t nb, int izc, int nharm_max,
                           const float *thr_host, DevCand *cands, uint32_t *count, uint32_t cap,
                           hipStream_t st);
+
+// Candidate finishing: sort the first min(*count, cap) records by
+// (nharm, k, iz) and write public records (r, z, FP64 significance) to out.
+// scratch: cand_sort_scratch_bytes(cap) bytes.
+size_t cand_sort_scratch_bytes(uint32_t cap);
+hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch,
+                                    double zmax, double dz, fdas_cand *out, hipStream_t st);
 
 }  // namespace fdas

@@ -82,7 +82,7 @@ namespace fdas {
 
 static int64_t buffer_bytes(const fdas_plan_s *core, int64_t nsamp) {
     const Geometry g = make_geometry(nsamp, core->S, core->h, core->W);
-    return series_bytes(g, core->S, core->nz) + nsamp * 4 + core->opts.cand_capacity * int64_t(sizeof(DevCand)) + 64;
+    return series_bytes(g, core->S, core->nz) + nsamp * 4 + candidate_bytes(core->cand_cap);
 }
 
 static void free_buffers(Buffers *b) {
@@ -109,24 +109,12 @@ static void scheduler(fdas_server_s *sv) {
                 res.status = FDAS_E_DEVICE;
                 res.error = std::string("request failed: ") + hipGetErrorString(q);
             } else {
-                const uint32_t found = *ws.h_count;
-                const int64_t got = std::min<int64_t>(found, sv->core->opts.cand_capacity);
-                hipError_t e = hipSuccess;
-                if (got > 0) {
-                    e = hipMemcpyAsync(ws.h_cands, ws.cands, size_t(got) * sizeof(DevCand), hipMemcpyDeviceToHost,
-                                       sl.stream);
-                    if (e == hipSuccess) e = hipStreamSynchronize(sl.stream);
-                }
-                if (e != hipSuccess) {
-                    res.status = FDAS_E_DEVICE;
-                    res.error = hipGetErrorString(e);
-                } else {
-                    res.cands.resize(size_t(got));
-                    int64_t n = 0;
-                    res.status = finish_candidates(sv->core, found, ws.h_cands, res.cands.data(), got, &n);
-                    res.found = n;
-                    if (res.status != FDAS_OK) res.error = g_last_error;
-                }
+                const int64_t n = std::min<int64_t>(*ws.h_count, sv->core->cand_cap);
+                res.cands.resize(size_t(n));
+                int64_t found = 0;
+                res.status = copy_candidates(sv->core, ws, res.cands.data(), n, &found, sl.stream);
+                res.found = found;
+                if (res.status != FDAS_OK) res.error = g_last_error;
             }
             res.latency = std::chrono::duration<double>(clk::now() - sl.req.t_submit).count();
             std::lock_guard<std::mutex> lk(sv->mu);
