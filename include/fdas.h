@@ -137,7 +137,9 @@ void fdas_plan_destroy(fdas_plan_t *plan);
  *                   complete when the stream is).
  * Errors: INVAL, DEVICE, OVERFLOW (cap or cand_capacity too small: the first
  * min(cap, found) candidates in sorted order of those captured are returned
- * and *ncands holds the true count). */
+ * and *ncands holds the true count; also when the internal list of cells
+ * reaching a threshold, 4 x cand_capacity long, overflowed, in which case the
+ * candidates are incomplete and *ncands is a lower bound). */
 fdas_status fdas_search(fdas_plan_t *plan, int32_t in_kind, const void *in_dev,
                         float *plane_dev, fdas_cand *cands_host, int64_t cap,
                         int64_t *ncands, void *hip_stream);
@@ -160,6 +162,16 @@ fdas_status fdas_plan_stage_times(const fdas_plan_t *plan, double *ms_out, int64
 fdas_status fdas_search_batch(fdas_plan_t *plan, int32_t n, const float *const *series_dev,
                               const int64_t *nsamp, fdas_cand *cands_host, const int64_t *cap,
                               int64_t *ncands, void *hip_stream);
+
+/* Autotuner for many-trial use: times the segment DFTs plus the fused
+ * correlation for every segment length in {2048, 4096, 8192} that is >= 4h
+ * and templates per workgroup in {7, 13, 26}, on a seeded synthetic noise
+ * series of nsamp samples, and returns the fastest (seg, templates per block)
+ * and its time in ms.  cache_path (may be NULL) names a text file of earlier
+ * results keyed by (GPU arch, nsamp, nz, h); a hit skips the measurement, a
+ * miss appends the new result.  Needs a GPU; allocates temporary plans. */
+fdas_status fdas_autotune(const fdas_bank *bank, int64_t nsamp, const fdas_opts *opts,
+                          const char *cache_path, int32_t *seg_out, int32_t *tpb_out, double *ms_out);
 
 /* Test hook: copy the last search's normalised spectrum (c64[Nb]) and block
  * medians (double[ceil(Nb/W)]) to device buffers; either pointer may be NULL. */

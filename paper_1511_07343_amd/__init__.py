@@ -16,7 +16,7 @@ import numpy as np
 
 __all__ = [
     "FdasError", "load", "lib_path", "CAND_DTYPE", "Bank", "Plan", "Server",
-    "make_templates", "threshold", "significance", "dft_c64", "IN_SERIES", "IN_SPECTRUM",
+    "make_templates", "autotune", "threshold", "significance", "dft_c64", "pinned_candidates", "IN_SERIES", "IN_SPECTRUM",
     "IN_SPECTRUM_NORMALISED",
 ]
 
@@ -92,6 +92,8 @@ def load():
         "fdas_plan_enable_timing": (_c_i32, [_c_vp, _c_i32]),
         "fdas_plan_stage_times": (_c_i32, [_c_vp, P(_c_dbl), P(_c_i64)]),
         "fdas_dft_c64": (_c_i32, [_c_i32, _c_i32, _c_i64, _c_vp, _c_vp, _c_vp]),
+        "fdas_autotune": (_c_i32, [_c_vp, _c_i64, P(_Opts), ctypes.c_char_p, P(_c_i32), P(_c_i32),
+                                   P(_c_dbl)]),
         "fdas_server_create": (_c_i32, [_c_vp, _c_i32, P(_Opts), _c_i64, ctypes.c_size_t, _c_i32,
                                         P(_c_vp)]),
         "fdas_submit": (_c_i32, [_c_vp, _c_vp, _c_i64, ctypes.c_uint64]),
@@ -215,6 +217,19 @@ def make_templates(zmax: float, dz: float) -> Bank:
     return Bank(zmax, dz)
 
 
+def autotune(bank: Bank, nsamp: int, cache_path: Optional[str] = None, **opts):
+    """Fastest (segment length, templates per block, ms) for this bank and
+    series length (see fdas_autotune)."""
+    seg = ctypes.c_int32()
+    tpb = ctypes.c_int32()
+    ms = ctypes.c_double()
+    o = _opts(**opts)
+    _check(load().fdas_autotune(bank.handle, int(nsamp), ctypes.byref(o),
+                                cache_path.encode() if cache_path else None, ctypes.byref(seg),
+                                ctypes.byref(tpb), ctypes.byref(ms)))
+    return seg.value, tpb.value, ms.value
+
+
 class Plan:
     """Device-resident plan for one (bank, nsamp, seg)."""
 
@@ -237,32 +252,44 @@ class Plan:
         return load().fdas_plan_device_bytes(self._h)
 
     def search(self, inp, kind: int = IN_SERIES, plane=None, cap: int = 1 << 22, stream=None,
-               allow_overflow: bool = False):
-        """Run the hot path on a device tensor; returns (candidates, n_found)."""
-        buf = self._buf.get(max(cap, 1))
+               allow_overflow: bool = False, out: Optional[np.ndarray] = None):
+        """Run the hot path on a device tensor; returns (candidates, n_found).
+
+        ``out``: optional CAND_DTYPE array (e.g. from ``pinned_candidates``)
+        that receives the records; the result is then a view of it.
+        """
+        buf = out if out is not None else self._buf.get(max(cap, 1))
+        if out is not None:
+            cap = min(cap, out.shape[0])
         n = ctypes.c_int64()
         st = load().fdas_search(self._h, kind, ctypes.c_void_p(inp.data_ptr()),
                                 ctypes.c_void_p(plane.data_ptr() if plane is not None else 0),
                                 _CandBuffer.ptr(buf), cap, ctypes.byref(n), _stream_handle(stream))
         _check(st, allow=(-4,) if allow_overflow else ())
-        return buf[:min(n.value, cap)].copy(), n.value
+        m = min(n.value, cap)
+        return (buf[:m] if out is not None else buf[:m].copy()), n.value
 
-    def search_batch(self, series: Sequence, caps: Optional[Sequence[int]] = None, stream=None):
-        """Several device float32 series; returns a list of candidate arrays."""
+    def search_batch(self, series: Sequence, caps: Optional[Sequence[int]] = None, stream=None,
+                     out: Optional[np.ndarray] = None):
+        """Several device float32 series; returns a list of candidate arrays
+        (views of ``out`` when given, which must hold sum(caps) records)."""
         k = len(series)
         caps = list(caps) if caps is not None else [1 << 20] * k
         ptrs = (ctypes.c_void_p * k)(*[s.data_ptr() for s in series])
         ns = (ctypes.c_int64 * k)(*[int(s.numel()) for s in series])
         cp = (ctypes.c_int64 * k)(*caps)
         nc = (ctypes.c_int64 * k)()
-        buf = self._buf.get(max(1, sum(caps)))
+        if out is not None and out.shape[0] < sum(caps):
+            raise ValueError("out holds fewer records than sum(caps)")
+        buf = out if out is not None else self._buf.get(max(1, sum(caps)))
         _check(load().fdas_search_batch(self._h, k, ptrs, ns, _CandBuffer.ptr(buf), cp, nc,
                                         _stream_handle(stream)))
-        out, off = [], 0
+        res, off = [], 0
         for i in range(k):
-            out.append(buf[off: off + min(nc[i], caps[i])].copy())
+            v = buf[off: off + min(nc[i], caps[i])]
+            res.append(v if out is not None else v.copy())
             off += caps[i]
-        return out
+        return res
 
     def fetch_spectrum(self, spectrum=None, medians=None, stream=None):
         _check(load().fdas_plan_fetch_spectrum(
@@ -337,6 +364,22 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+class _PinnedArray(np.ndarray):
+    """ndarray that keeps the torch tensor owning its page-locked memory alive."""
+
+    owner = None
+
+
+def pinned_candidates(n: int):
+    """A CAND_DTYPE array of n records in page-locked host memory (torch
+    allocates it), for fast device-to-host candidate copies."""
+    import torch
+    t = torch.empty(n * CAND_DTYPE.itemsize, dtype=torch.uint8, pin_memory=True)
+    arr = t.numpy().view(CAND_DTYPE).view(_PinnedArray)
+    arr.owner = t
+    return arr
 
 
 def dft_c64(x, inverse: bool = False, out=None, stream=None):

@@ -34,7 +34,7 @@ CXX_FLAGS = [
 ]
 
 HIP_SOURCES = ["kernels.hip", "candidates.hip"]
-CXX_SOURCES = ["host_math.cpp", "fdas_capi.cpp", "batch.cpp", "server.cpp"]
+CXX_SOURCES = ["host_math.cpp", "fdas_capi.cpp", "batch.cpp", "server.cpp", "autotune.cpp"]
 
 
 def _run(cmd):

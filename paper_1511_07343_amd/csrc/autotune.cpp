@@ -1,0 +1,131 @@
+// Autotuner over the overlap-save segment length and the templates per
+// correlation workgroup.  The harmonic sums do not depend on either, so each
+// candidate is scored by the time of the segment DFTs plus the fused
+// correlation on a synthetic white-noise series of the requested length.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <iomanip>
+#include <random>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "capi_internal.hpp"
+
+using namespace fdas;
+
+namespace {
+
+std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a(prop.gcnArchName);
+    const size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+bool cache_lookup(const char *path, const std::string &key, int32_t *seg, int32_t *tpb, double *ms) {
+    if (!path) return false;
+    std::ifstream in(path);
+    std::string line;
+    while (std::getline(in, line)) {
+        if (line.rfind(key + " ", 0) != 0) continue;
+        std::istringstream ss(line.substr(key.size()));
+        int32_t s = 0, t = 0;
+        double m = 0.0;
+        if (ss >> s >> t >> m) {
+            *seg = s;
+            *tpb = t;
+            *ms = m;
+            return true;
+        }
+    }
+    return false;
+}
+
+}  // namespace
+
+extern "C" fdas_status fdas_autotune(const fdas_bank *bank, int64_t nsamp, const fdas_opts *opts,
+                                     const char *cache_path, int32_t *seg_out, int32_t *tpb_out, double *ms_out) {
+    if (!bank || !seg_out || !tpb_out) {
+        set_error("bank and outputs must not be NULL");
+        return FDAS_E_INVAL;
+    }
+    fdas_opts o;
+    if (opts) o = *opts; else fdas_default_opts(&o);
+    fdas_status st = validate_opts(o);
+    if (st != FDAS_OK) return st;
+    st = check_nsamp(nsamp, 0, bank->h);
+    if (st != FDAS_OK) return st;
+    char keybuf[160];
+    std::snprintf(keybuf, sizeof(keybuf), "%s nsamp=%lld nz=%d h=%d", arch_name().c_str(), (long long)nsamp,
+                  bank->nz, bank->h);
+    const std::string key(keybuf);
+    double ms_cached = 0.0;
+    if (cache_lookup(cache_path, key, seg_out, tpb_out, &ms_cached)) {
+        if (ms_out) *ms_out = ms_cached;
+        return FDAS_OK;
+    }
+    // synthetic input: seeded white noise
+    std::vector<float> host(static_cast<size_t>(nsamp));
+    std::mt19937_64 rng(12345);
+    std::normal_distribution<float> nd(0.f, 1.f);
+    for (auto &v : host) v = nd(rng);
+    float *dx = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&dx), size_t(nsamp) * 4);
+    if (e != hipSuccess) {
+        set_error("autotune: device allocation failed");
+        return FDAS_E_NOMEM;
+    }
+    e = hipMemcpy(dx, host.data(), size_t(nsamp) * 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dx);
+        return hip_fail(nullptr, e, "autotune upload");
+    }
+    double best = INFINITY;
+    int32_t best_seg = 0, best_tpb = 0;
+    const int32_t tpbs[] = {7, 13, 26};
+    std::vector<fdas_cand> cands(1);
+    for (int32_t seg = 2048; seg <= 8192; seg *= 2) {
+        if (seg < 4 * bank->h) continue;
+        fdas_plan_t *p = nullptr;
+        st = fdas_plan(bank, nsamp, seg, &o, &p);
+        if (st != FDAS_OK) continue;
+        for (int32_t tpb : tpbs) {
+            p->tpb = tpb;
+            int64_t n = 0;
+            st = fdas_search(p, FDAS_IN_SERIES_F32, dx, nullptr, cands.data(), 0, &n, nullptr);  // warm-up
+            if (st != FDAS_OK && st != FDAS_E_OVERFLOW) break;
+            if (fdas_plan_enable_timing(p, 1) != FDAS_OK) break;
+            for (int r = 0; r < 3; ++r) (void)fdas_search(p, FDAS_IN_SERIES_F32, dx, nullptr, cands.data(), 0, &n, nullptr);
+            double ms[FDAS_NSTAGES];
+            int64_t nt = 0;
+            (void)fdas_plan_stage_times(p, ms, &nt);
+            (void)fdas_plan_enable_timing(p, 0);
+            if (nt <= 0) break;
+            const double score = (ms[2] + ms[3]) / double(nt);
+            if (score < best) {
+                best = score;
+                best_seg = seg;
+                best_tpb = tpb;
+            }
+        }
+        fdas_plan_destroy(p);
+    }
+    (void)hipFree(dx);
+    if (!best_seg) {
+        set_error("autotune: no candidate configuration ran");
+        return FDAS_E_DEVICE;
+    }
+    *seg_out = best_seg;
+    *tpb_out = best_tpb;
+    if (ms_out) *ms_out = best;
+    if (cache_path) {
+        std::ofstream out(cache_path, std::ios::app);
+        if (out) out << key << " " << best_seg << " " << best_tpb << " " << std::setprecision(17) << best << "\n";
+    }
+    return FDAS_OK;
+}

@@ -1,6 +1,9 @@
 // fdas_search_batch: many series through the hot path with consecutive trials
 // on two streams and two work buffers, so that one trial's memory-bound
-// harmonic sum runs beside the next trial's ALU-bound correlation.
+// harmonic sum runs beside the next trial's ALU-bound correlation.  Each
+// slot's per-trial launch sequence is captured once per series length in a
+// HIP graph that reads the workspace's own input buffer; a trial is a
+// device-to-device copy into that buffer followed by a graph launch.
 #include <algorithm>
 #include <string>
 
@@ -14,6 +17,13 @@ static fdas_status ensure_batch_resources(fdas_plan_s *p) {
             fdas_status s = alloc_workspace(p, p->ws[i], p->nsamp);
             if (s != FDAS_OK) return s;
         }
+        if (!p->ws[i].series) {
+            hipError_t e = hipMalloc(reinterpret_cast<void **>(&p->ws[i].series), size_t(p->nsamp) * 4);
+            if (e != hipSuccess) {
+                set_error("hipMalloc batch input buffer");
+                return FDAS_E_NOMEM;
+            }
+        }
         if (!p->aux[i]) {
             hipError_t e = hipStreamCreateWithFlags(&p->aux[i], hipStreamNonBlocking);
             if (e != hipSuccess) return hip_fail(p, e, "stream create");
@@ -25,6 +35,35 @@ static fdas_status ensure_batch_resources(fdas_plan_s *p) {
             if (e != hipSuccess) return hip_fail(p, e, "event create");
         }
     }
+    return FDAS_OK;
+}
+
+// The captured launch sequence of one trial of length nsamp on slot i.
+static fdas_status slot_graph(fdas_plan_s *p, int i, int64_t nsamp, hipGraphExec_t *out) {
+    auto it = p->graphs[size_t(i)].find(nsamp);
+    if (it != p->graphs[size_t(i)].end()) {
+        *out = it->second;
+        return FDAS_OK;
+    }
+    Workspace &ws = p->ws[size_t(i)];
+    hipStream_t st = p->aux[size_t(i)];
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(p, e, "begin capture");
+    const Geometry g = make_geometry(nsamp, p->S, p->h, p->W);
+    fdas_status s = enqueue_search(p, ws, g, FDAS_IN_SERIES_F32, ws.series, ws.plane, ws.cands, ws.count, st);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(st, &graph);
+    if (s != FDAS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return s;
+    }
+    if (e != hipSuccess) return hip_fail(p, e, "end capture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(p, e, "graph instantiate");
+    p->graphs[size_t(i)][nsamp] = exec;
+    *out = exec;
     return FDAS_OK;
 }
 
@@ -100,11 +139,16 @@ extern "C" fdas_status fdas_search_batch(fdas_plan_t *plan, int32_t n, const flo
             if (first_err != FDAS_OK) break;
         }
         Workspace &ws = plan->ws[slot];
-        const Geometry g = make_geometry(nsamp[i], plan->S, plan->h, plan->W);
-        first_err = enqueue_search(plan, ws, g, FDAS_IN_SERIES_F32, series_dev[i], ws.plane, ws.cands, ws.count,
-                                   plan->aux[slot]);
+        hipGraphExec_t exec = nullptr;
+        first_err = slot_graph(plan, slot, nsamp[i], &exec);
         if (first_err != FDAS_OK) break;
-        e = hipMemcpyAsync(ws.h_count, ws.count, 4, hipMemcpyDeviceToHost, plan->aux[slot]);
+        e = hipMemcpyAsync(ws.series, series_dev[i], size_t(nsamp[i]) * 4, hipMemcpyDeviceToDevice, plan->aux[slot]);
+        if (e == hipSuccess) e = hipGraphLaunch(exec, plan->aux[slot]);
+        if (e != hipSuccess) {
+            first_err = hip_fail(plan, e, "batch trial launch");
+            break;
+        }
+        e = hipMemcpyAsync(ws.h_count, ws.count, 12, hipMemcpyDeviceToHost, plan->aux[slot]);
         if (e != hipSuccess) {
             first_err = hip_fail(plan, e, "copy candidate count");
             break;

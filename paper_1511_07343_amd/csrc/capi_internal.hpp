@@ -5,6 +5,7 @@
 
 #include <array>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -36,9 +37,11 @@ struct Workspace {
     float *plane = nullptr;  // f-fdot plane, nz x nb
     DevCand *cands = nullptr;     // unordered records from the harmonic-sum kernel
     uint32_t *count = nullptr;    // their count (may exceed the capacity)
+    void *hits = nullptr;         // cells reaching a threshold (harmonic-sum pass 1)
     void *sort = nullptr;         // radix-sort scratch
     fdas_cand *final = nullptr;   // sorted public records
     uint32_t *h_count = nullptr;  // pinned host copy of the count
+    float *series = nullptr;      // graph input: the trial is copied here first (batched path)
 };
 
 }  // namespace fdas
@@ -49,6 +52,7 @@ struct fdas_plan_s {
     int32_t nz = 0, h = 0, izc = 0, S = 0, log2s = 0, W = 1024, tpb = 13;
     int64_t nsamp = 0;
     uint32_t cand_cap = 0;  // device candidate capacity (records)
+    uint32_t hit_cap = 0;   // device capacity of the threshold-hit list
     int device = 0;
     double thr_d[5] = {};
     float thr_f[5] = {};
@@ -56,6 +60,8 @@ struct fdas_plan_s {
     std::array<fdas::Workspace, 2> ws{};
     std::array<hipStream_t, 2> aux{};
     std::array<hipEvent_t, 4> events{};
+    // batched path: captured per-trial launch sequence, per slot and length
+    std::array<std::map<int64_t, hipGraphExec_t>, 2> graphs{};
     bool broken = false;
     // stage timing (fdas_plan_enable_timing)
     bool timing = false;

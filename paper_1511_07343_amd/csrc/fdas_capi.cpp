@@ -87,7 +87,8 @@ int64_t series_bytes(const Geometry &g, int32_t S, int32_t nz) {
 }
 
 int64_t candidate_bytes(uint32_t cap) {
-    return int64_t(cap) * int64_t(sizeof(DevCand) + sizeof(fdas_cand)) + int64_t(cand_sort_scratch_bytes(cap)) + 64;
+    return int64_t(cap) * int64_t(sizeof(DevCand) + sizeof(fdas_cand) + 4 * hit_record_bytes()) +
+           int64_t(cand_sort_scratch_bytes(cap)) + 64;
 }
 
 // Run the whole per-series path on `st`, writing the plane into `plane` and
@@ -126,9 +127,10 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
     e = launch_correlate(ws.seg, p->d_bank, p->nz, p->tpb, g.nb, p->log2s, p->h, g.nseg, plane, st);
     if (e != hipSuccess) return hip_fail(p, e, "correlate");
     if ((e = mark(4)) != hipSuccess) return hip_fail(p, e, "timing event");
-    e = launch_zero_u32(dcount, 1, st);
+    e = launch_zero_u32(dcount, 3, st);
     if (e != hipSuccess) return hip_fail(p, e, "zero counter");
-    e = launch_harmsum(plane, p->nz, g.nb, p->izc, p->opts.nharm_max, p->thr_f, dcands, dcount, p->cand_cap, st);
+    e = launch_harmsum(plane, p->nz, g.nb, p->izc, p->opts.nharm_max, p->thr_f, ws.hits, p->hit_cap, dcands, dcount,
+                       p->cand_cap, st);
     if (e != hipSuccess) return hip_fail(p, e, "harmonic sum");
     e = launch_finish_candidates(dcands, dcount, p->cand_cap, ws.sort, p->zmax, p->dz, ws.final, st);
     if (e != hipSuccess) return hip_fail(p, e, "candidate sort");
@@ -153,7 +155,8 @@ fdas_status accumulate_timing(fdas_plan_s *p) {
 
 fdas_status copy_candidates(const fdas_plan_s *p, const Workspace &ws, fdas_cand *out, int64_t cap,
                             int64_t *ncands, hipStream_t st) {
-    const uint32_t found = *ws.h_count;
+    const uint32_t found = ws.h_count[0];
+    const bool hits_lost = ws.h_count[2] != 0;
     const int64_t n = std::min<int64_t>(std::min<int64_t>(found, p->cand_cap), cap);
     if (n > 0) {
         hipError_t e = hipMemcpyAsync(out, ws.final, size_t(n) * sizeof(fdas_cand), hipMemcpyDeviceToHost, st);
@@ -161,6 +164,10 @@ fdas_status copy_candidates(const fdas_plan_s *p, const Workspace &ws, fdas_cand
         if (e != hipSuccess) return hip_fail(const_cast<fdas_plan_s *>(p), e, "copy candidates");
     }
     if (ncands) *ncands = found;
+    if (hits_lost) {
+        set_error("threshold-hit list capacity exceeded: candidates incomplete (raise cand_capacity)");
+        return FDAS_E_OVERFLOW;
+    }
     if (int64_t(found) > cap || found > p->cand_cap) {
         set_error("candidate capacity exceeded");
         return FDAS_E_OVERFLOW;
@@ -178,8 +185,10 @@ static void free_workspace(Workspace &ws) {
     if (ws.cands) (void)hipFree(ws.cands);
     if (ws.count) (void)hipFree(ws.count);
     if (ws.sort) (void)hipFree(ws.sort);
+    if (ws.hits) (void)hipFree(ws.hits);
     if (ws.final) (void)hipFree(ws.final);
     if (ws.h_count) (void)hipHostFree(ws.h_count);
+    if (ws.series) (void)hipFree(ws.series);
     ws = Workspace{};
 }
 
@@ -203,6 +212,7 @@ fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp) {
     FDAS_ALLOC(ws.cands, int64_t(p->cand_cap) * int64_t(sizeof(DevCand)));
     FDAS_ALLOC(ws.count, 64);
     FDAS_ALLOC(ws.sort, cand_sort_scratch_bytes(p->cand_cap));
+    FDAS_ALLOC(ws.hits, int64_t(p->hit_cap) * int64_t(hit_record_bytes()));
     FDAS_ALLOC(ws.final, int64_t(p->cand_cap) * int64_t(sizeof(fdas_cand)));
 #undef FDAS_ALLOC
     e = hipHostMalloc(reinterpret_cast<void **>(&ws.h_count), 64, hipHostMallocDefault);
@@ -220,7 +230,7 @@ void destroy_workspace(Workspace &ws) { free_workspace(ws); }
 // Candidates of a search enqueued on st: counter, then records, to the host.
 fdas_status collect(fdas_plan_s *p, Workspace &ws, fdas_cand *out, int64_t cap, int64_t *ncands,
                     hipStream_t st) {
-    hipError_t e = hipMemcpyAsync(ws.h_count, ws.count, 4, hipMemcpyDeviceToHost, st);
+    hipError_t e = hipMemcpyAsync(ws.h_count, ws.count, 12, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return hip_fail(p, e, "copy candidate count");
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(p, e, "search");
@@ -268,6 +278,7 @@ fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, 
                                ? o.cand_capacity
                                : std::min<int64_t>(int64_t(1) << 22,
                                                    std::max<int64_t>(int64_t(1) << 16, int64_t(bank->nz) * (nsamp / 2) / 256)));
+    p->hit_cap = uint32_t(std::min<int64_t>(int64_t(p->cand_cap) * 4, int64_t(1) << 30));
     int levels = 0;
     while ((1 << levels) < o.nharm_max) ++levels;
     for (int l = 0; l < 5; ++l) {
@@ -444,6 +455,8 @@ void fdas_plan_destroy(fdas_plan_t *plan) {
         if (ev) (void)hipEventDestroy(ev);
         ev = nullptr;
     }
+    for (auto &m : plan->graphs)
+        for (auto &kv : m) (void)hipGraphExecDestroy(kv.second);
     if (plan->d_bank) (void)hipFree(plan->d_bank);
     delete plan;
 }

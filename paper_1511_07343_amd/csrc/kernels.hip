@@ -20,6 +20,9 @@ constexpr int fft_threads(int log2s) {
     return log2s >= 12 ? 256 : log2s == 11 ? 128 : log2s >= 8 ? 64 : 32;
 }
 
+// Threads per workgroup of the fused correlation kernel.
+constexpr int corr_threads(int log2s) { return fft_threads(log2s); }
+
 // 8 XCDs on MI355X; workgroups are dispatched to XCDs round-robin by index.
 constexpr int kXcds = 8;
 
@@ -254,10 +257,10 @@ __global__ __launch_bounds__(256) void k_normalise(const float2 *__restrict__ X,
 // item u = (i mod 8) * per + i div 8, so each XCD walks a contiguous range of
 // template blocks over all segments and keeps its templates in its own L2.
 template <int LOG2S>
-__global__ __launch_bounds__(fft_threads(LOG2S), 2) void k_correlate(
+__global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
     const float2 *__restrict__ segspec, const float2 *__restrict__ bank, int nz, int tpb, int64_t nb,
     int h, int64_t nseg, int64_t total, int64_t per, float *__restrict__ plane) {
-    using Sh = FftShape<LOG2S, fft_threads(LOG2S)>;
+    using Sh = FftShape<LOG2S, corr_threads(LOG2S)>;
     __shared__ float2 lds[Sh::LDS_FLOAT2];
     const int t = threadIdx.x;
     const int64_t u = int64_t(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
@@ -301,81 +304,21 @@ struct Thr {
     float v[5];
 };
 
-// Sums over 2^0 .. 2^levels harmonics with the top harmonic at (iz, k):
-// S_nh = sum_{j=1}^{nh} P[iz_j][k_j], k_j = floor((2 j k + nh) / (2 nh)),
-// iz_j = izc + sgn(d) floor((2 |d| j + nh) / (2 nh)), d = iz - izc.
-// Even j of S_nh are the cells of S_{nh/2}, so each level adds its odd j.
-__device__ __forceinline__ void harm_sums(const float *__restrict__ P, int64_t nb, int izc, int iz,
-                                          int k, int levels, float (&s)[5]) {
-    const int d = iz - izc;
+// Every term of every level is a fraction j/16 of the top harmonic
+// (j = 1..16, level l >= 1 adds the odd multiples of 16 / 2^l; the cell
+// itself is j = 16):
+//   column c_j(k) = floor((j k + 8) / 16),
+//   row    r_j(iz) = izc + sgn(d) floor((|d| j + 8) / 16),  d = iz - izc,
+// the rounding (half away from zero) of k j/16 and d j/16, i.e. of
+// k j'/nh and d j'/nh for the j'-th harmonic of an nh-harmonic sum.
+__device__ __forceinline__ int frac_row(int izc, int d, int j) {
     const int ad = d < 0 ? -d : d;
-    const int sg = d < 0 ? -1 : 1;
-    float acc = P[int64_t(iz) * nb + k];
-    s[0] = acc;
-    for (int l = 1; l <= levels; ++l) {
-        const int nh = 1 << l;
-        float add = 0.f;
-        for (int j = 1; j < nh; j += 2) {
-            const int kj = (2 * j * k + nh) / (2 * nh);
-            const int izj = izc + sg * ((2 * ad * j + nh) / (2 * nh));
-            add += P[int64_t(izj) * nb + kj];
-        }
-        acc += add;
-        s[l] = acc;
-    }
+    const int off = (ad * j + 8) >> 4;
+    return d < 0 ? izc - off : izc + off;
 }
 
-constexpr int kHsThreads = 256;
-
-__global__ __launch_bounds__(kHsThreads) void k_harmsum(const float *__restrict__ P, int nz, int64_t nb,
-                                                        int izc, int levels, Thr thr,
-                                                        DevCand *__restrict__ cands,
-                                                        uint32_t *__restrict__ count, uint32_t cap) {
-    const int64_t kk = int64_t(blockIdx.x) * kHsThreads + threadIdx.x;
-    const int iz = blockIdx.y;
-    if (kk >= nb) return;
-    const int k = int(kk);
-    float s[5];
-    harm_sums(P, nb, izc, iz, k, levels, s);
-    for (int l = 0; l <= levels; ++l) {
-        if (!(s[l] >= thr.v[l])) continue;
-        bool peak = true;
-        for (int di = -1; di <= 1 && peak; ++di) {
-            const int iz2 = iz + di;
-            if (iz2 < 0 || iz2 >= nz) continue;
-            for (int dk = -1; dk <= 1; ++dk) {
-                if (di == 0 && dk == 0) continue;
-                const int64_t k2 = kk + dk;
-                if (k2 < 0 || k2 >= nb) continue;
-                float s2[5];
-                harm_sums(P, nb, izc, iz2, int(k2), l, s2);
-                const bool earlier = di < 0 || (di == 0 && dk < 0);
-                if (earlier ? !(s[l] > s2[l]) : !(s[l] >= s2[l])) {
-                    peak = false;
-                    break;
-                }
-            }
-        }
-        if (!peak) continue;
-        const uint32_t slot = atomicAdd(count, 1u);
-        if (slot < cap) cands[slot] = DevCand{k, iz, 1 << l, s[l]};
-    }
-}
-
-// Harmonic sums, second form.  A wave owns 8 columns per lane,
-// k = k0 + lane + 64 i (i < 8), and walks HS_TZ consecutive rows.  Every term
-// of every level is a fraction j/16 of the top harmonic (j = 1..16):
-//   column c_j(k) = floor((j k + 8) / 16),  row r_j(iz) = izc + sgn(d) floor((|d| j + 8) / 16),
-// and since 64 i j / 16 = 4 j i, c_j(k0 + lane + 64 i) = c_j(k0 + lane) + 4 j i:
-// each fraction needs one base address per lane and 8 loads at compile-time
-// offsets.  The 8 values of fraction j are kept in registers and reloaded
-// only when r_j changes between consecutive rows (wave-uniform test).
-constexpr int HS_C = 8;
-constexpr int HS_TZ = 16;
-constexpr int HS_WAVES = 4;
-
-// S_1, S_2, ..., S_2^LEVELS from the 16 fraction values v[j] (v[0] unused),
-// in one fixed order shared by the fast path and the neighbour checks.
+// S_1, S_2, ..., S_2^LEVELS from the 16 fraction terms v[j] (v[0] unused),
+// always in this one summation order.
 template <int LEVELS>
 __device__ __forceinline__ void nested_sums(const float (&v)[17], float (&s)[5]) {
     s[0] = v[16];
@@ -387,21 +330,15 @@ __device__ __forceinline__ void nested_sums(const float (&v)[17], float (&s)[5])
 
 template <int LEVELS>
 __device__ __forceinline__ constexpr bool frac_used(int j) {
-    // level l uses the odd multiples of 16 / 2^l
     return (j % (16 >> LEVELS)) == 0;
 }
 
-__device__ __forceinline__ int frac_row(int izc, int d, int j) {
-    const int ad = d < 0 ? -d : d;
-    const int off = (ad * j + 8) >> 4;
-    return d < 0 ? izc - off : izc + off;
-}
-
-// All levels at one cell, loading its terms directly (neighbour checks).
+// All levels at one cell, loading its terms directly from the plane.
 template <int LEVELS>
-__device__ __forceinline__ void cell_sums2(const float *__restrict__ P, int64_t nb, int izc, int iz, int k,
-                                           float (&s)[5]) {
+__device__ __forceinline__ void cell_sums(const float *__restrict__ P, int64_t nb, int izc, int iz, int k,
+                                          float (&s)[5]) {
     float v[17];
+    v[0] = 0.f;
     const int d = iz - izc;
     static_for<1, 17>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
@@ -411,10 +348,41 @@ __device__ __forceinline__ void cell_sums2(const float *__restrict__ P, int64_t 
     nested_sums<LEVELS>(v, s);
 }
 
+// Append the lanes with `pred` to a list through one atomic per wave.
+__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t *__restrict__ counter, int lane, bool &taken) {
+    const uint64_t mask = __ballot(pred);
+    taken = false;
+    if (!mask) return 0;
+    const int leader = __ffsll((long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, uint32_t(__popcll(mask)));
+    base = __shfl(base, leader);
+    taken = pred;
+    return base + uint32_t(__popcll(mask & ((uint64_t(1) << lane) - 1)));
+}
+
+// Pass 1: sums of every cell, thresholds, and a list of the cells that reach
+// the threshold of any level ("hits": column, row, level mask).
+// A wave owns columns k = k0 + lane + 64 i (i < HS_C) and walks HS_TZ
+// consecutive rows.  With kl = k0 + lane, c_j(kl + 64 i) = c_j(kl) + 4 j i:
+// one base address per fraction and compile-time offsets.  The HS_C values of
+// fraction j stay in registers and are reloaded only when r_j moves between
+// consecutive rows (a wave-uniform test).
+constexpr int HS_C = 4;
+constexpr int HS_TZ = 16;
+constexpr int HS_WAVES = 4;
+
+struct Hit {
+    int32_t k;
+    uint32_t iz_mask;  // row in bits 0..15, level mask in bits 16..20
+};
+
 template <int LEVELS>
-__global__ __launch_bounds__(64 * HS_WAVES) void k_harmsum2(const float *__restrict__ P, int nz, int64_t nb,
-                                                            int izc, Thr thr, DevCand *__restrict__ cands,
-                                                            uint32_t *__restrict__ count, uint32_t cap) {
+__global__ __launch_bounds__(64 * HS_WAVES) void k_hits(const float *__restrict__ P, int nz, int64_t nb, int izc,
+                                                        Thr thr, Hit *__restrict__ hits,
+                                                        uint32_t *__restrict__ hit_count, uint32_t hit_cap) {
+    // nb is a multiple of 64 * HS_C (checked at launch): a wave's columns are
+    // all inside the plane or all outside it.
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int64_t k0 = (int64_t(blockIdx.x) * HS_WAVES + wave) * (64 * HS_C);
@@ -423,70 +391,99 @@ __global__ __launch_bounds__(64 * HS_WAVES) void k_harmsum2(const float *__restr
     const int iz1 = min(nz, iz0 + HS_TZ);
     const int kl = int(k0) + lane;
     float val[17][HS_C];
-    int rowc[17];
-#pragma unroll
-    for (int j = 0; j < 17; ++j) rowc[j] = -1;
     for (int iz = iz0; iz < iz1; ++iz) {
         const int d = iz - izc;
+        int klo = kl;  // recomputing the column bases per row is cheaper than holding them
+        asm volatile("" : "+v"(klo));
         static_for<1, 17>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
             if constexpr (frac_used<LEVELS>(j)) {
                 const int row = frac_row(izc, d, j);
-                if (row != rowc[j]) {
-                    rowc[j] = row;
-                    const float *__restrict__ src = P + int64_t(row) * nb + ((j * kl + 8) >> 4);
+                if (iz == iz0 || row != frac_row(izc, d - 1, j)) {
+                    const float *__restrict__ src = P + int64_t(row) * nb + ((j * klo + 8) >> 4);
 #pragma unroll
-                    for (int i = 0; i < HS_C; ++i)
-                        val[j][i] = (kl + 64 * i < nb) ? src[4 * j * i] : 0.f;
+                    for (int i = 0; i < HS_C; ++i) val[j][i] = src[4 * j * i];
                 }
             }
         });
-        // fast path: which (cell, level) pairs reach their threshold
-        uint64_t hits = 0;
 #pragma unroll
         for (int i = 0; i < HS_C; ++i) {
             float v[17];
             v[0] = 0.f;
 #pragma unroll
             for (int j = 1; j < 17; ++j) v[j] = val[j][i];
-            float s[5];
-            nested_sums<LEVELS>(v, s);
+            float sm[5];
+            nested_sums<LEVELS>(v, sm);
+            uint32_t mask = 0;
 #pragma unroll
-            for (int l = 0; l <= LEVELS; ++l)
-                if (s[l] >= thr.v[l]) hits |= uint64_t(1) << (5 * i + l);
-        }
-        // rare: check the 3x3 neighbourhood of each hit (sums recomputed from
-        // the same loads in the same order, so they equal the fast path's)
-        while (hits) {
-            const int b = __ffsll((long long)hits) - 1;
-            hits &= hits - 1;
-            const int i = b / 5, l = b % 5;
-            const int k = kl + 64 * i;
-            if (int64_t(k) >= nb) continue;
-            float s[5];
-            cell_sums2<LEVELS>(P, nb, izc, iz, k, s);
-            bool peak = true;
-            for (int di = -1; di <= 1 && peak; ++di) {
-                const int iz2 = iz + di;
-                if (iz2 < 0 || iz2 >= nz) continue;
-                for (int dk = -1; dk <= 1; ++dk) {
-                    if (di == 0 && dk == 0) continue;
-                    const int k2 = k + dk;
-                    if (k2 < 0 || int64_t(k2) >= nb) continue;
-                    float s2[5];
-                    cell_sums2<LEVELS>(P, nb, izc, iz2, k2, s2);
-                    const bool earlier = di < 0 || (di == 0 && dk < 0);
-                    if (earlier ? !(s[l] > s2[l]) : !(s[l] >= s2[l])) {
-                        peak = false;
-                        break;
-                    }
-                }
-            }
-            if (!peak) continue;
-            const uint32_t slot = atomicAdd(count, 1u);
-            if (slot < cap) cands[slot] = DevCand{k, iz, 1 << l, s[l]};
+            for (int l = 0; l <= LEVELS; ++l) mask |= (sm[l] >= thr.v[l] ? 1u : 0u) << l;
+            bool taken;
+            const uint32_t slot = wave_append(mask != 0, hit_count, lane, taken);
+            if (taken && slot < hit_cap) hits[slot] = Hit{kl + 64 * i, uint32_t(iz) | (mask << 16)};
         }
     }
+}
+
+// Pass 2, one hit per lane: recompute the hit cell's sums and its 8
+// neighbours' (same loads, same order as pass 1) and keep, for every level in
+// the mask, a 3x3 local maximum: strictly greater than the neighbours earlier
+// in row-major (iz, k) order, at least equal to the later ones; neighbours
+// outside the plane are ignored.
+template <int LEVELS>
+__global__ __launch_bounds__(256) void k_peaks(const float *__restrict__ P, int nz, int64_t nb, int izc,
+                                               const Hit *__restrict__ hits, const uint32_t *__restrict__ hit_count,
+                                               uint32_t hit_cap, DevCand *__restrict__ cands,
+                                               uint32_t *__restrict__ count, uint32_t cap) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t n = min(*hit_count, hit_cap);
+    const uint32_t stride = gridDim.x * blockDim.x;
+    // whole waves iterate together so that the appends stay wave-wide
+    for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n; base += stride) {
+        const uint32_t h = base + lane;
+        const bool valid = h < n;
+        int k = 0, iz = 0;
+        uint32_t mask = 0;
+        if (valid) {
+            const Hit r = hits[h];
+            k = r.k;
+            iz = int(r.iz_mask & 0xffffu);
+            mask = r.iz_mask >> 16;
+        }
+        float s[5];
+        cell_sums<LEVELS>(P, nb, izc, iz, k, s);
+#pragma unroll 1
+        for (int di = -1; di <= 1; ++di) {
+            const int iz2 = iz + di;
+            const bool rin = iz2 >= 0 && iz2 < nz;
+#pragma unroll
+            for (int dk = -1; dk <= 1; ++dk) {
+                if (di == 0 && dk == 0) continue;
+                const int k2 = k + dk;
+                const bool in = valid && rin && k2 >= 0 && int64_t(k2) < nb;
+                float s2[5];
+                cell_sums<LEVELS>(P, nb, izc, in ? iz2 : iz, in ? k2 : k, s2);
+                const bool earlier = di < 0 || (di == 0 && dk < 0);
+#pragma unroll
+                for (int l = 0; l <= LEVELS; ++l) {
+                    const bool beaten = earlier ? !(s[l] > s2[l]) : !(s[l] >= s2[l]);
+                    if (in && beaten) mask &= ~(1u << l);
+                }
+            }
+        }
+#pragma unroll
+        for (int l = 0; l <= LEVELS; ++l) {
+            bool taken;
+            const uint32_t slot = wave_append(valid && ((mask >> l) & 1u), count, lane, taken);
+            if (taken && slot < cap) cands[slot] = DevCand{k, iz, 1 << l, s[l]};
+        }
+    }
+}
+
+// A hit list that overflowed makes the candidate list incomplete: raise a flag
+// the host turns into OVERFLOW.
+__global__ void k_flag_hit_overflow(const uint32_t *__restrict__ hit_count, uint32_t hit_cap,
+                                    uint32_t *__restrict__ flag) {
+    if (threadIdx.x == 0 && *hit_count > hit_cap) *flag = 1u;
 }
 
 __global__ void k_zero_u32(uint32_t *__restrict__ p, int n) {
@@ -595,7 +592,7 @@ hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, i
     const int64_t grid = per * kXcds;
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
 #define CALL(L)                                                                                       \
-    hipLaunchKernelGGL((k_correlate<L>), dim3(unsigned(grid)), dim3(fft_threads(L)), 0, st, segspec, bank, \
+    hipLaunchKernelGGL((k_correlate<L>), dim3(unsigned(grid)), dim3(corr_threads(L)), 0, st, segspec, bank, \
                        nz, tpb, nb, h, nseg, total, per, plane);
     FDAS_SWITCH_LOG2(log2s, CALL)
 #undef CALL
@@ -603,17 +600,24 @@ hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, i
 }
 
 hipError_t launch_harmsum(const float *plane, int nz, int64_t nb, int izc, int nharm_max, const float *thr_host,
-                          DevCand *cands, uint32_t *count, uint32_t cap, hipStream_t st) {
+                          void *hit_buf, uint32_t hit_cap, DevCand *cands, uint32_t *count, uint32_t cap,
+                          hipStream_t st) {
     int levels = 0;
     while ((1 << levels) < nharm_max) ++levels;
     if ((1 << levels) != nharm_max || levels > 4) return hipErrorInvalidValue;
-    if (nb > (int64_t(1) << 26)) return hipErrorInvalidValue;
+    if (nb > (int64_t(1) << 26) || nb % (64 * HS_C) != 0 || nz > 65535) return hipErrorInvalidValue;
     Thr thr{};
     for (int l = 0; l <= levels; ++l) thr.v[l] = thr_host[l];
+    Hit *hits = static_cast<Hit *>(hit_buf);
+    uint32_t *hit_count = count + 1;  // the counter pair is zeroed by the caller
     const int64_t cols = 64 * HS_C * HS_WAVES;
-    const dim3 grid(unsigned((nb + cols - 1) / cols), unsigned((nz + HS_TZ - 1) / HS_TZ));
-#define CALL(L) \
-    hipLaunchKernelGGL((k_harmsum2<L>), grid, dim3(64 * HS_WAVES), 0, st, plane, nz, nb, izc, thr, cands, count, cap);
+    const dim3 grid1(unsigned((nb + cols - 1) / cols), unsigned((nz + HS_TZ - 1) / HS_TZ));
+    const unsigned grid2 = 2048;
+#define CALL(LV)                                                                                                \
+    hipLaunchKernelGGL((k_hits<LV>), grid1, dim3(64 * HS_WAVES), 0, st, plane, nz, nb, izc, thr, hits, hit_count, \
+                       hit_cap);                                                                               \
+    hipLaunchKernelGGL((k_peaks<LV>), dim3(grid2), dim3(256), 0, st, plane, nz, nb, izc, hits, hit_count, hit_cap,  \
+                       cands, count, cap);
     switch (levels) {
         case 0: CALL(0); break;
         case 1: CALL(1); break;
@@ -622,7 +626,10 @@ hipError_t launch_harmsum(const float *plane, int nz, int64_t nb, int izc, int n
         default: CALL(4); break;
     }
 #undef CALL
+    hipLaunchKernelGGL(k_flag_hit_overflow, dim3(1), dim3(64), 0, st, hit_count, hit_cap, count + 2);
     return hipGetLastError();
 }
+
+size_t hit_record_bytes() { return sizeof(Hit); }
 
 }  // namespace fdas

@@ -50,13 +50,18 @@ hipError_t launch_normalise(const float2 *X, const double *med, int W, int64_t n
 hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, int tpb, int64_t nb,
                             int log2s, int h, int64_t nseg, float *plane, hipStream_t st);
 
-// Harmonic sums over 1..nharm_max harmonics, threshold and 3x3 local maxima.
-// thr[i] is the threshold of 2^i harmonics.  Appends to cands (capacity cap)
-// through the counter *count (which must start at 0; it ends holding the true
-// number found).
-hipError_t launch_harmsum(const float *plane, int nz, int64_t nb, int izc, int nharm_max,
-                          const float *thr_host, DevCand *cands, uint32_t *count, uint32_t cap,
+// Harmonic sums over 1..nharm_max harmonics, thresholds and 3x3 local
+// maxima.  thr[i] is the threshold of 2^i harmonics.  Two passes: every
+// cell's sums with a list of the cells reaching any threshold (hit_buf, room
+// for hit_cap records of hit_record_bytes()), then the neighbour test for
+// every listed cell.  Appends to cands (capacity cap) through count[0]; the
+// hit list's counter is count[1]; count[2] is set to 1 if the hit list
+// overflowed (the candidates are then incomplete).  All three must start at
+// 0.  nb must be a multiple of 256, nz at most 65535.
+hipError_t launch_harmsum(const float *plane, int nz, int64_t nb, int izc, int nharm_max, const float *thr_host,
+                          void *hit_buf, uint32_t hit_cap, DevCand *cands, uint32_t *count, uint32_t cap,
                           hipStream_t st);
+size_t hit_record_bytes();
 
 // Candidate finishing: sort the first min(*count, cap) records by
 // (nharm, k, iz) and write public records (r, z, FP64 significance) to out.

@@ -185,6 +185,19 @@ def test_candidate_overflow_reports_true_count(gpu_lib):
     bank.close()
 
 
+def test_hit_list_overflow_is_reported(gpu_lib):
+    # a tiny capacity makes the internal list of threshold-passing cells
+    # overflow; the search must say so rather than return a silent subset
+    t = synth.make_series(1 << 15, seed=13)
+    bank = gpu_lib.make_templates(10.0, 2.0)
+    plan = gpu_lib.Plan(bank, 1 << 15, 256, nharm_max=4, sigma=2.0, median_window=256, cand_capacity=16)
+    with pytest.raises(gpu_lib.FdasError) as e:
+        plan.search(_dev(t.x), cap=1000)
+    assert e.value.status == -4
+    plan.close()
+    bank.close()
+
+
 def test_repeat_is_bit_identical(gpu_lib):
     t = synth.make_series(1 << 16, seed=11)
     a = _run(gpu_lib, t.x, 20.0, 2.0, 512, nharm_max=16, sigma=4.0)
@@ -202,6 +215,10 @@ def test_batch_equals_single(gpu_lib):
     plan = gpu_lib.Plan(bank, 1 << 16, 512, **opts)
     xs = [_dev(t.x) for t in trials]
     got = plan.search_batch(xs, caps=[20000] * len(xs))
+    # the captured graphs are replayed with other inputs in between
+    again = plan.search_batch(xs[::-1], caps=[20000] * len(xs))[::-1]
+    for a, b in zip(got, again):
+        assert np.array_equal(a, b)
     for t, x, g in zip(trials, xs, got):
         single = gpu_lib.Plan(bank, t.nsamp, 512, **opts)
         want, n = single.search(x, cap=20000)
@@ -235,6 +252,35 @@ def test_server_alone_vs_mix(gpu_lib):
     srv.close()
     for i in range(len(trials)):
         assert np.array_equal(seen[1000 + i], alone[i])
+
+
+def test_autotune_and_cache(gpu_lib, tmp_path):
+    bank = gpu_lib.make_templates(50.0, 2.0)  # h = 41: every segment length is valid
+    cache = str(tmp_path / "tune.txt")
+    seg, tpb, ms = gpu_lib.autotune(bank, 1 << 16, cache_path=cache, nharm_max=4)
+    assert seg in (2048, 4096, 8192) and tpb in (7, 13, 26) and ms > 0
+    assert len(open(cache).read().splitlines()) == 1
+    assert gpu_lib.autotune(bank, 1 << 16, cache_path=cache, nharm_max=4) == (seg, tpb, ms)
+    # a plan with the tuned shape gives the same candidates as the default one
+    t = synth.make_series(1 << 16, seed=70, pulsars=[synth.Pulsar(r=4000.2, z=9.0, amp=0.1, nharm=2)])
+    x = _dev(t.x)
+    a = gpu_lib.Plan(bank, 1 << 16, seg, nharm_max=4, templates_per_block=tpb).search(x)[0]
+    b = gpu_lib.Plan(bank, 1 << 16, 1024, nharm_max=4).search(x)[0]
+    assert np.array_equal(a[["nharm", "k", "iz"]], b[["nharm", "k", "iz"]])
+    bank.close()
+
+
+def test_pinned_output_buffer(gpu_lib):
+    t = synth.make_series(1 << 15, seed=71)
+    bank = gpu_lib.make_templates(10.0, 2.0)
+    plan = gpu_lib.Plan(bank, 1 << 15, 256, nharm_max=4, sigma=3.0, median_window=256)
+    x = _dev(t.x)
+    ref, n = plan.search(x)
+    out = gpu_lib.pinned_candidates(1 << 16)
+    got, n2 = plan.search(x, out=out)
+    assert n2 == n and np.array_equal(got, ref)
+    plan.close()
+    bank.close()
 
 
 def test_server_small_budget_queues(gpu_lib):
