@@ -128,7 +128,8 @@ void fdas_plan_destroy(fdas_plan_t *plan);
  * and peaks):
  *   in_kind/in_dev  device input: float32[nsamp] series, or c64[Nb] spectrum
  *                   (caller-owned, read-only).
- *   plane_dev       NULL, or device float32[nz][Nb] that receives the plane.
+ *   plane_dev       NULL, or device float32[nz][Nb] that receives the plane
+ *                   (16-byte aligned, else INVAL).
  *   cands_host      host array of cap entries; receives candidates sorted by
  *                   (nharm, k, iz).  May be NULL when cap is 0.
  *   ncands          receives the number of candidates found.
@@ -138,8 +139,9 @@ void fdas_plan_destroy(fdas_plan_t *plan);
  * Errors: INVAL, DEVICE, OVERFLOW (cap or cand_capacity too small: the first
  * min(cap, found) candidates in sorted order of those captured are returned
  * and *ncands holds the true count; also when the internal list of cells
- * reaching a threshold, 4 x cand_capacity long, overflowed, in which case the
- * candidates are incomplete and *ncands is a lower bound). */
+ * that may reach a threshold (4 x cand_capacity cells in 2 x cand_capacity
+ * groups of 16 columns) overflowed, in which case the candidates are
+ * incomplete and *ncands is a lower bound). */
 fdas_status fdas_search(fdas_plan_t *plan, int32_t in_kind, const void *in_dev,
                         float *plane_dev, fdas_cand *cands_host, int64_t cap,
                         int64_t *ncands, void *hip_stream);

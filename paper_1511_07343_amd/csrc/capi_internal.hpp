@@ -35,9 +35,10 @@ struct Workspace {
     double *med = nullptr;   // block medians of |X|^2
     float2 *seg = nullptr;   // segment spectra, nseg x S
     float *plane = nullptr;  // f-fdot plane, nz x nb
+    uint8_t *codes = nullptr;  // screening codes of the plane, nz x nb
     DevCand *cands = nullptr;     // unordered records from the harmonic-sum kernel
     uint32_t *count = nullptr;    // their count (may exceed the capacity)
-    void *hits = nullptr;         // cells reaching a threshold (harmonic-sum pass 1)
+    void *hits = nullptr;         // harmonic-sum screen lists, exact sums and group map
     void *sort = nullptr;         // radix-sort scratch
     fdas_cand *final = nullptr;   // sorted public records
     uint32_t *h_count = nullptr;  // pinned host copy of the count
@@ -52,10 +53,13 @@ struct fdas_plan_s {
     int32_t nz = 0, h = 0, izc = 0, S = 0, log2s = 0, W = 1024, tpb = 13;
     int64_t nsamp = 0;
     uint32_t cand_cap = 0;  // device candidate capacity (records)
-    uint32_t hit_cap = 0;   // device capacity of the threshold-hit list
+    uint32_t hit_cap = 0;   // device capacity of the harmonic-sum screen's cell list
+    uint32_t group_cap = 0; // ... and of its group list
     int device = 0;
     double thr_d[5] = {};
     float thr_f[5] = {};
+    float code_inv = 1.f;       // 1 / delta of the screening codes
+    uint32_t code_thr[5] = {};  // screen thresholds in code units
     float2 *d_bank = nullptr;  // nz x S, segment domain, scaled by 1/S
     std::array<fdas::Workspace, 2> ws{};
     std::array<hipStream_t, 2> aux{};
@@ -83,7 +87,7 @@ fdas_status validate_opts(const fdas_opts &o);
 fdas_status check_nsamp(int64_t nsamp, int32_t seg, int32_t h);
 Geometry make_geometry(int64_t nsamp, int32_t S, int32_t h, int32_t W);
 int64_t series_bytes(const Geometry &g, int32_t S, int32_t nz);
-int64_t candidate_bytes(uint32_t cap);
+int64_t candidate_bytes(const fdas_plan_s *p, int64_t nb);
 fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp);
 void destroy_workspace(Workspace &ws);
 fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &g, int32_t in_kind,

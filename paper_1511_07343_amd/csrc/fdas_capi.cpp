@@ -80,15 +80,18 @@ Geometry make_geometry(int64_t nsamp, int32_t S, int32_t h, int32_t W) {
 }
 
 // Device bytes of the per-series buffers (spectrum scratch, medians, segment
-// spectra, plane) for a given geometry.
+// spectra, plane and its screening codes) for a given geometry.
 int64_t series_bytes(const Geometry &g, int32_t S, int32_t nz) {
     const int64_t M = g.nb;
-    return 3 * M * 8 + g.nblk * 8 + g.nseg * int64_t(S) * 8 + int64_t(nz) * g.nb * 4;
+    return 3 * M * 8 + g.nblk * 8 + g.nseg * int64_t(S) * 8 + int64_t(nz) * g.nb * 5;
 }
 
-int64_t candidate_bytes(uint32_t cap) {
-    return int64_t(cap) * int64_t(sizeof(DevCand) + sizeof(fdas_cand) + 4 * hit_record_bytes()) +
-           int64_t(cand_sort_scratch_bytes(cap)) + 64;
+// Device bytes of the candidate buffers and the harmonic-sum lists of a plan
+// for a series of nb bins.
+int64_t candidate_bytes(const fdas_plan_s *p, int64_t nb) {
+    const uint32_t cap = p->cand_cap;
+    return int64_t(cap) * int64_t(sizeof(DevCand) + sizeof(fdas_cand)) + int64_t(cand_sort_scratch_bytes(cap)) +
+           int64_t(harmsum_scratch_bytes(p->nz, nb, p->hit_cap, p->group_cap)) + 64;
 }
 
 // Run the whole per-series path on `st`, writing the plane into `plane` and
@@ -124,13 +127,14 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
     e = launch_segfft(X, med, p->W, g.nb, p->log2s, p->h, g.nseg, ws.seg, st);
     if (e != hipSuccess) return hip_fail(p, e, "segment DFT");
     if ((e = mark(3)) != hipSuccess) return hip_fail(p, e, "timing event");
-    e = launch_correlate(ws.seg, p->d_bank, p->nz, p->tpb, g.nb, p->log2s, p->h, g.nseg, plane, st);
+    e = launch_correlate(ws.seg, p->d_bank, p->nz, p->tpb, g.nb, p->log2s, p->h, g.nseg, plane, ws.codes,
+                         p->code_inv, st);
     if (e != hipSuccess) return hip_fail(p, e, "correlate");
     if ((e = mark(4)) != hipSuccess) return hip_fail(p, e, "timing event");
-    e = launch_zero_u32(dcount, 3, st);
+    e = launch_zero_u32(dcount, 4, st);
     if (e != hipSuccess) return hip_fail(p, e, "zero counter");
-    e = launch_harmsum(plane, p->nz, g.nb, p->izc, p->opts.nharm_max, p->thr_f, ws.hits, p->hit_cap, dcands, dcount,
-                       p->cand_cap, st);
+    e = launch_harmsum(plane, ws.codes, p->nz, g.nb, p->izc, p->opts.nharm_max, p->thr_f, p->code_thr, ws.hits,
+                       p->hit_cap, p->group_cap, dcands, dcount, p->cand_cap, st);
     if (e != hipSuccess) return hip_fail(p, e, "harmonic sum");
     e = launch_finish_candidates(dcands, dcount, p->cand_cap, ws.sort, p->zmax, p->dz, ws.final, st);
     if (e != hipSuccess) return hip_fail(p, e, "candidate sort");
@@ -165,7 +169,7 @@ fdas_status copy_candidates(const fdas_plan_s *p, const Workspace &ws, fdas_cand
     }
     if (ncands) *ncands = found;
     if (hits_lost) {
-        set_error("threshold-hit list capacity exceeded: candidates incomplete (raise cand_capacity)");
+        set_error("harmonic-sum cell list capacity exceeded: candidates incomplete (raise cand_capacity)");
         return FDAS_E_OVERFLOW;
     }
     if (int64_t(found) > cap || found > p->cand_cap) {
@@ -182,6 +186,7 @@ static void free_workspace(Workspace &ws) {
     if (ws.med) (void)hipFree(ws.med);
     if (ws.seg) (void)hipFree(ws.seg);
     if (ws.plane) (void)hipFree(ws.plane);
+    if (ws.codes) (void)hipFree(ws.codes);
     if (ws.cands) (void)hipFree(ws.cands);
     if (ws.count) (void)hipFree(ws.count);
     if (ws.sort) (void)hipFree(ws.sort);
@@ -209,10 +214,11 @@ fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp) {
     FDAS_ALLOC(ws.med, g.nblk * 8);
     FDAS_ALLOC(ws.seg, g.nseg * int64_t(p->S) * 8);
     FDAS_ALLOC(ws.plane, int64_t(p->nz) * g.nb * 4);
+    FDAS_ALLOC(ws.codes, int64_t(p->nz) * g.nb);
     FDAS_ALLOC(ws.cands, int64_t(p->cand_cap) * int64_t(sizeof(DevCand)));
     FDAS_ALLOC(ws.count, 64);
     FDAS_ALLOC(ws.sort, cand_sort_scratch_bytes(p->cand_cap));
-    FDAS_ALLOC(ws.hits, int64_t(p->hit_cap) * int64_t(hit_record_bytes()));
+    FDAS_ALLOC(ws.hits, harmsum_scratch_bytes(p->nz, g.nb, p->hit_cap, p->group_cap));
     FDAS_ALLOC(ws.final, int64_t(p->cand_cap) * int64_t(sizeof(fdas_cand)));
 #undef FDAS_ALLOC
     e = hipHostMalloc(reinterpret_cast<void **>(&ws.h_count), 64, hipHostMallocDefault);
@@ -279,11 +285,23 @@ fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, 
                                : std::min<int64_t>(int64_t(1) << 22,
                                                    std::max<int64_t>(int64_t(1) << 16, int64_t(bank->nz) * (nsamp / 2) / 256)));
     p->hit_cap = uint32_t(std::min<int64_t>(int64_t(p->cand_cap) * 4, int64_t(1) << 30));
+    p->group_cap = std::max<uint32_t>(p->hit_cap / 2, 1u);
     int levels = 0;
     while ((1 << levels) < o.nharm_max) ++levels;
     for (int l = 0; l < 5; ++l) {
         p->thr_d[l] = l <= levels ? threshold(o.sigma, 1 << l) : INFINITY;
         p->thr_f[l] = float(p->thr_d[l]);
+    }
+    // Screening codes: delta = thr_max / 250, so a saturated code (255) clears
+    // every level.  An exact FP32 sum S >= thr_f has code sum >= S / delta up to
+    // a few roundings (< 2e-6 relative), hence >= floor(thr_f / delta (1 - 1e-5)).
+    // Thresholds near zero (very low sigma) make every cell pass the screen.
+    const double inv = 250.0 / double(p->thr_f[levels]);
+    const bool screen = inv > 0.0 && inv < 1e30;
+    p->code_inv = screen ? float(inv) : 1.f;
+    for (int l = 0; l < 5; ++l) {
+        const double t = double(p->thr_f[l]) * double(p->code_inv) * (1.0 - 1e-5);
+        p->code_thr[l] = l > levels ? 0x8000u : screen && t > 0.0 ? uint32_t(std::floor(t)) : 0u;
     }
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) {
@@ -436,7 +454,7 @@ int64_t fdas_plan_device_bytes(const fdas_plan_t *plan) {
     for (const Workspace &ws : plan->ws)
         if (ws.nsamp)
             b += series_bytes(make_geometry(ws.nsamp, plan->S, plan->h, plan->W), plan->S, plan->nz) +
-                 candidate_bytes(plan->cand_cap);
+                 candidate_bytes(plan, ws.nsamp / 2);
     return b;
 }
 
@@ -469,6 +487,10 @@ fdas_status fdas_search(fdas_plan_t *plan, int32_t in_kind, const void *in_dev, 
     }
     if (in_kind < FDAS_IN_SERIES_F32 || in_kind > FDAS_IN_SPECTRUM_C64_NORMALISED) {
         set_error("bad input kind");
+        return FDAS_E_INVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(plane_dev) % 16 != 0) {
+        set_error("plane_dev must be 16-byte aligned");
         return FDAS_E_INVAL;
     }
     if (plan->broken) {

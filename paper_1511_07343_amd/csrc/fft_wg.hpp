@@ -29,10 +29,13 @@ namespace fdas {
 // ------------------------------------------------------------------ complex
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// Products with their fused multiply-adds written out, so that the rounding
+// of a result does not depend on how the compiler contracts the surrounding
+// code (one multiply, then one fma, in this order).
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
-__device__ __forceinline__ float cnorm(float2 a) { return a.x * a.x + a.y * a.y; }
+__device__ __forceinline__ float cnorm(float2 a) { return fmaf(a.x, a.x, a.y * a.y); }
 
 // ----------------------------------------------------- compile-time helpers
 template <int I, int E, class F>

@@ -253,13 +253,21 @@ __global__ __launch_bounds__(256) void k_normalise(const float2 *__restrict__ X,
 }
 
 // ----------------------------------------------- fused correlation kernel
+// Screening code of a power: min(255, ceil(P / delta)) with code_inv = 1 / delta,
+// never below P / delta (up to one rounding of the product), so integer sums of
+// codes bound power sums from above; NaN and huge powers saturate at 255.
+__device__ __forceinline__ uint8_t power_code(float pw, float code_inv) {
+    return uint8_t(fminf(ceilf(pw * code_inv), 255.f));
+}
+
 // Work item u = (template block tb, segment s), tb-major.  Workgroup i runs
 // item u = (i mod 8) * per + i div 8, so each XCD walks a contiguous range of
 // template blocks over all segments and keeps its templates in its own L2.
 template <int LOG2S>
 __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
     const float2 *__restrict__ segspec, const float2 *__restrict__ bank, int nz, int tpb, int64_t nb,
-    int h, int64_t nseg, int64_t total, int64_t per, float *__restrict__ plane) {
+    int h, int64_t nseg, int64_t total, int64_t per, float *__restrict__ plane, uint8_t *__restrict__ codes,
+    float code_inv) {
     using Sh = FftShape<LOG2S, corr_threads(LOG2S)>;
     __shared__ float2 lds[Sh::LDS_FLOAT2];
     const int t = threadIdx.x;
@@ -280,6 +288,7 @@ __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
     const int64_t kbase = s * L - h;  // plane column of segment point n is kbase + n
     // columns [kbase + h, kend) of the plane come from this segment
     const int nend = int(min(int64_t(Sh::S - h), nb - kbase));
+    const int sh = int(((kbase % 4) + 4) % 4);  // plane row offset of point 0 modulo 4
     for (int iz = iz0; iz < iz1; ++iz) {
         // Keep the per-point offsets inside the loop: hoisting the 32 addresses
         // of each operand out of it would cost more registers than recomputing.
@@ -291,11 +300,36 @@ __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
         for (int m = 0; m < Sh::R; ++m) v[m] = cmul(sp[to + Sh::NT * m], bz[to + Sh::NT * m]);
         fft_wg<Sh, +1>(v, lds, tw, t);
         float *__restrict__ row = plane + int64_t(iz) * nb + kbase;
+        uint8_t *__restrict__ qrow = codes + int64_t(iz) * nb + kbase;
+        // Powers through LDS so that each thread stores 4 consecutive
+        // points: point n sits at LDS index n + sh, which puts chunk c
+        // (indices 4c .. 4c+3) on a 16-byte boundary of the plane row.
+        float *__restrict__ lf = reinterpret_cast<float *>(lds);
 #pragma unroll
-        for (int m = 0; m < Sh::R; ++m) {
-            const int n = to + Sh::NT * m;
-            if (n >= h && n < nend) row[n] = cnorm(v[m]);
+        for (int m = 0; m < Sh::R; ++m) lf[sh + to + Sh::NT * m] = cnorm(v[m]);
+        __syncthreads();
+        constexpr int NCH = (Sh::S + 6) / 4;  // chunks covering indices [0, S + 3)
+        for (int c = t; c < NCH; c += Sh::NT) {
+            const int n0 = 4 * c - sh;
+            const float4 p4 = *reinterpret_cast<const float4 *>(lf + 4 * c);
+            if (n0 >= h && n0 + 4 <= nend) {
+                *reinterpret_cast<float4 *>(row + n0) = p4;
+                *reinterpret_cast<uint32_t *>(qrow + n0) =
+                    uint32_t(power_code(p4.x, code_inv)) | (uint32_t(power_code(p4.y, code_inv)) << 8) |
+                    (uint32_t(power_code(p4.z, code_inv)) << 16) | (uint32_t(power_code(p4.w, code_inv)) << 24);
+            } else {
+                const float pe[4] = {p4.x, p4.y, p4.z, p4.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int n = n0 + e;
+                    if (n >= h && n < nend) {
+                        row[n] = pe[e];
+                        qrow[n] = power_code(pe[e], code_inv);
+                    }
+                }
+            }
         }
+        __syncthreads();  // the next transform writes lds
     }
 }
 
@@ -361,129 +395,285 @@ __device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t *__restrict_
     return base + uint32_t(__popcll(mask & ((uint64_t(1) << lane) - 1)));
 }
 
-// Pass 1: sums of every cell, thresholds, and a list of the cells that reach
-// the threshold of any level ("hits": column, row, level mask).
-// A wave owns columns k = k0 + lane + 64 i (i < HS_C) and walks HS_TZ
-// consecutive rows.  With kl = k0 + lane, c_j(kl + 64 i) = c_j(kl) + 4 j i:
-// one base address per fraction and compile-time offsets.  The HS_C values of
-// fraction j stay in registers and are reloaded only when r_j moves between
-// consecutive rows (a wave-uniform test).
-constexpr int HS_C = 4;
-constexpr int HS_TZ = 16;
-constexpr int HS_WAVES = 4;
+// Pass 1, the screen: every cell's sums on the code plane (see power_code).
+// A cell's integer code sum is at least its power sum / delta, so a cell
+// whose code sums stay below T_l = floor(thr_l / delta (1 - 1e-5)) at every
+// level cannot reach any threshold.  Cells that may ("flagged" cells) are
+// listed per group of 16 columns of one row: a group record holds the row,
+// the group, a 16-bit mask of its flagged cells and the index of its first
+// flagged cell in the cell arrays; group_map[iz][m] holds the record index of
+// group (m, iz).  Map entries are written only for flagged groups and are
+// trusted only when the record they point to names the same group, so the
+// map needs no clearing between searches.
+//
+// A lane owns the 16 consecutive columns k = 16 m + i (i < 16) of a row.
+// Since 16 m j is a multiple of 16, fraction j of column 16 m + i is
+// j m + c_j(i): the 16 codes of fraction j sit in bytes [j m, j m + c_j(15)]
+// of row r_j, at compile-time offsets c_j(i) from j m.  Cells 2p and 2p+1
+// share one 32-bit register (p < 8), one per 16-bit half: a sum of at most 16
+// codes (<= 4080) never carries into the upper half, and a half reaches
+// level l iff sum + 0x8000 - T_l sets its bit 15.  All loads of a row are
+// independent of each other and issued together.
+constexpr int SC_TZ = 8;      // rows per wave
+constexpr int SC_WAVES = 4;   // waves per workgroup
+constexpr int SC_COLS = 16;   // columns per lane (one group)
+constexpr int SC_WAVE_COLS = 64 * SC_COLS;
 
-struct Hit {
-    int32_t k;
-    uint32_t iz_mask;  // row in bits 0..15, level mask in bits 16..20
+struct ScreenThr {
+    uint32_t k[5];  // (0x8000 - T_l) in both 16-bit halves
 };
 
+struct Group {
+    int32_t m;         // columns 16 m .. 16 m + 15
+    uint32_t iz_mask;  // row in bits 0..15, flagged cells in bits 16..31
+    uint32_t first;    // index of the first flagged cell in the cell arrays
+    uint32_t pad;
+};
+
+// Counters (zeroed before the pass): candidates, flagged cells, overflow
+// flag, groups.
+enum { CNT_CANDS = 0, CNT_CELLS = 1, CNT_OVERFLOW = 2, CNT_GROUPS = 3 };
+
+// Byte layout of one fraction's 16 codes.
+template <int J>
+struct FracBytes {
+    static constexpr int off(int i) { return (J * i + 8) >> 4; }          // c_j(i)
+    static constexpr int span = off(15) + 1;                              // bytes used
+    static constexpr int maxshift = J % 4 == 0 ? 0 : J % 2 == 0 ? 2 : 3;  // (j m) mod 4
+    static constexpr int nd = (maxshift + span + 3) / 4;                  // dwords loaded
+    static constexpr int nw = (span + 3) / 4;                             // aligned words
+};
+
+// Level group of fraction j: the level that first adds it (16 -> 0, 8 -> 1,
+// 4 and 12 -> 2, 2 mod 4 -> 3, odd -> 4).
+constexpr int frac_level(int j) { return j == 16 ? 0 : j % 2 ? 4 : j % 4 ? 3 : j % 8 ? 2 : 1; }
+
+// Add the 8 packed pairs of fraction J (lane's group m of row qrow) to acc.
+template <int J>
+__device__ __forceinline__ void add_fraction(const uint8_t *__restrict__ qrow, int64_t m, uint32_t (&acc)[8]) {
+    using FB = FracBytes<J>;
+    const int64_t b = int64_t(J) * m;  // first byte
+    const uint32_t *__restrict__ src = reinterpret_cast<const uint32_t *>(qrow + (b & ~int64_t(3)));
+    uint32_t d[FB::nd];
+#pragma unroll
+    for (int q = 0; q < FB::nd; ++q) d[q] = src[q];
+    uint32_t w[FB::nw];
+    if constexpr (FB::maxshift == 0) {
+#pragma unroll
+        for (int q = 0; q < FB::nw; ++q) w[q] = d[q];
+    } else {
+        const uint32_t sh = uint32_t(b & 3);
+#pragma unroll
+        for (int q = 0; q < FB::nw; ++q) w[q] = __builtin_amdgcn_alignbyte(d[q + 1 < FB::nd ? q + 1 : q], d[q], sh);
+    }
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        const int a = FB::off(2 * p), c = FB::off(2 * p + 1);
+        const int wa = a >> 2, wc = c >> 2;
+        // v_perm_b32 selector bytes: 0-3 pick bytes of the second source,
+        // 4-7 bytes of the first, 0x0c gives zero.
+        const uint32_t sel = uint32_t(a & 3) | 0x0c00u | (uint32_t((wc == wa ? 0 : 4) + (c & 3)) << 16) | 0x0c000000u;
+        acc[p] += __builtin_amdgcn_perm(w[wc], w[wa], sel);
+    }
+}
+
+// Inclusive prefix sum over the wave.
+__device__ __forceinline__ uint32_t wave_scan(uint32_t x, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    return x;
+}
+
 template <int LEVELS>
-__global__ __launch_bounds__(64 * HS_WAVES) void k_hits(const float *__restrict__ P, int nz, int64_t nb, int izc,
-                                                        Thr thr, Hit *__restrict__ hits,
-                                                        uint32_t *__restrict__ hit_count, uint32_t hit_cap) {
-    // nb is a multiple of 64 * HS_C (checked at launch): a wave's columns are
-    // all inside the plane or all outside it.
+__global__ __launch_bounds__(64 * SC_WAVES) void k_screen(const uint8_t *__restrict__ Q, int nz, int64_t nb,
+                                                          int izc, ScreenThr T, Group *__restrict__ groups,
+                                                          uint32_t *__restrict__ group_map, uint32_t *__restrict__ cnt,
+                                                          uint32_t group_cap, uint32_t cell_cap) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int64_t k0 = (int64_t(blockIdx.x) * HS_WAVES + wave) * (64 * HS_C);
-    if (k0 >= nb) return;
-    const int iz0 = blockIdx.y * HS_TZ;
-    const int iz1 = min(nz, iz0 + HS_TZ);
-    const int kl = int(k0) + lane;
-    float val[17][HS_C];
+    const int64_t m = (int64_t(blockIdx.x) * SC_WAVES + wave) * 64 + lane;  // column group
+    const int64_t ngr = nb / SC_COLS;
+    const bool valid = m < ngr;
+    if (!__any(valid)) return;
+    const int64_t mm = valid ? m : 0;  // lanes past the end read group 0 and report nothing
+    const int iz0 = blockIdx.y * SC_TZ;
+    const int iz1 = min(nz, iz0 + SC_TZ);
     for (int iz = iz0; iz < iz1; ++iz) {
         const int d = iz - izc;
-        int klo = kl;  // recomputing the column bases per row is cheaper than holding them
-        asm volatile("" : "+v"(klo));
+        uint32_t G[LEVELS + 1][8];
+#pragma unroll
+        for (int l = 0; l <= LEVELS; ++l)
+#pragma unroll
+            for (int p = 0; p < 8; ++p) G[l][p] = 0u;
         static_for<1, 17>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
-            if constexpr (frac_used<LEVELS>(j)) {
-                const int row = frac_row(izc, d, j);
-                if (iz == iz0 || row != frac_row(izc, d - 1, j)) {
-                    const float *__restrict__ src = P + int64_t(row) * nb + ((j * klo + 8) >> 4);
-#pragma unroll
-                    for (int i = 0; i < HS_C; ++i) val[j][i] = src[4 * j * i];
-                }
-            }
+            if constexpr (frac_used<LEVELS>(j))
+                add_fraction<j>(Q + int64_t(frac_row(izc, d, j)) * nb, mm, G[frac_level(j)]);
         });
+        uint32_t mask = 0;
 #pragma unroll
-        for (int i = 0; i < HS_C; ++i) {
-            float v[17];
-            v[0] = 0.f;
+        for (int p = 0; p < 8; ++p) {
+            uint32_t sm = G[0][p];
+            uint32_t fl = sm + T.k[0];
 #pragma unroll
-            for (int j = 1; j < 17; ++j) v[j] = val[j][i];
-            float sm[5];
-            nested_sums<LEVELS>(v, sm);
-            uint32_t mask = 0;
-#pragma unroll
-            for (int l = 0; l <= LEVELS; ++l) mask |= (sm[l] >= thr.v[l] ? 1u : 0u) << l;
-            bool taken;
-            const uint32_t slot = wave_append(mask != 0, hit_count, lane, taken);
-            if (taken && slot < hit_cap) hits[slot] = Hit{kl + 64 * i, uint32_t(iz) | (mask << 16)};
+            for (int l = 1; l <= LEVELS; ++l) {
+                sm += G[l][p];
+                fl |= sm + T.k[l];
+            }
+            mask |= ((fl >> 15) & 1u) << (2 * p);
+            mask |= (fl >> 31) << (2 * p + 1);
+        }
+        if (!valid) mask = 0;
+        if (!__any(mask != 0)) continue;
+        // one group record per lane with flagged cells; their cells get
+        // consecutive indices
+        const uint32_t ncell = __popc(mask);
+        const uint32_t incl = wave_scan(ncell, lane);
+        const uint32_t total = __shfl(incl, 63);
+        uint32_t cbase = 0;
+        if (lane == 0) cbase = atomicAdd(cnt + CNT_CELLS, total);
+        cbase = __shfl(cbase, 0);
+        bool taken;
+        const uint32_t g = wave_append(mask != 0, cnt + CNT_GROUPS, lane, taken);
+        const uint32_t first = cbase + incl - ncell;
+        // every record below min(count, group_cap) is written, with no cells
+        // when they do not fit (the overflow flag reports the loss)
+        if (taken && g < group_cap) {
+            const bool fits = uint64_t(first) + ncell <= cell_cap;
+            groups[g] = Group{int32_t(m), uint32_t(iz) | ((fits ? mask : 0u) << 16), first, 0u};
+            if (fits) group_map[int64_t(iz) * ngr + m] = g;
         }
     }
 }
 
-// Pass 2, one hit per lane: recompute the hit cell's sums and its 8
-// neighbours' (same loads, same order as pass 1) and keep, for every level in
-// the mask, a 3x3 local maximum: strictly greater than the neighbours earlier
-// in row-major (iz, k) order, at least equal to the later ones; neighbours
-// outside the plane are ignored.
+constexpr int SUM_STRIDE = 5;  // floats per flagged cell in the sums array
+
+// Pass 2: the exact FP32 sums of every flagged cell (16 lanes per group,
+// lane i on column 16 m + i), loaded from the plane in the one summation
+// order of nested_sums.
 template <int LEVELS>
-__global__ __launch_bounds__(256) void k_peaks(const float *__restrict__ P, int nz, int64_t nb, int izc,
-                                               const Hit *__restrict__ hits, const uint32_t *__restrict__ hit_count,
-                                               uint32_t hit_cap, DevCand *__restrict__ cands,
-                                               uint32_t *__restrict__ count, uint32_t cap) {
-    const int lane = threadIdx.x & 63;
-    const uint32_t n = min(*hit_count, hit_cap);
-    const uint32_t stride = gridDim.x * blockDim.x;
-    // whole waves iterate together so that the appends stay wave-wide
-    for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < n; base += stride) {
-        const uint32_t h = base + lane;
-        const bool valid = h < n;
-        int k = 0, iz = 0;
-        uint32_t mask = 0;
-        if (valid) {
-            const Hit r = hits[h];
-            k = r.k;
-            iz = int(r.iz_mask & 0xffffu);
-            mask = r.iz_mask >> 16;
-        }
+__global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int64_t nb, int izc,
+                                               const Group *__restrict__ groups, const uint32_t *__restrict__ cnt,
+                                               uint32_t group_cap, float *__restrict__ sums) {
+    const uint32_t ng = min(cnt[CNT_GROUPS], group_cap);
+    const int i = threadIdx.x & 15;
+    for (uint32_t g = (blockIdx.x * blockDim.x + threadIdx.x) >> 4; g < ng; g += (gridDim.x * blockDim.x) >> 4) {
+        const Group r = groups[g];
+        const uint32_t mask = r.iz_mask >> 16;
+        if (!((mask >> i) & 1u)) continue;
         float s[5];
-        cell_sums<LEVELS>(P, nb, izc, iz, k, s);
-#pragma unroll 1
-        for (int di = -1; di <= 1; ++di) {
-            const int iz2 = iz + di;
-            const bool rin = iz2 >= 0 && iz2 < nz;
+        cell_sums<LEVELS>(P, nb, izc, int(r.iz_mask & 0xffffu), r.m * SC_COLS + i, s);
+        float *__restrict__ o = sums + int64_t(r.first + __popc(mask & ((1u << i) - 1u))) * SUM_STRIDE;
 #pragma unroll
-            for (int dk = -1; dk <= 1; ++dk) {
-                if (di == 0 && dk == 0) continue;
-                const int k2 = k + dk;
-                const bool in = valid && rin && k2 >= 0 && int64_t(k2) < nb;
-                float s2[5];
-                cell_sums<LEVELS>(P, nb, izc, in ? iz2 : iz, in ? k2 : k, s2);
-                const bool earlier = di < 0 || (di == 0 && dk < 0);
+        for (int l = 0; l <= LEVELS; ++l) o[l] = s[l];
+    }
+}
+
+// Pass 3: thresholds and 3x3 local maxima on the exact sums (16 lanes per
+// group).  A cell keeps a level when its sum reaches the threshold and is
+// strictly greater than the neighbours earlier in row-major (iz, k) order and
+// at least equal to the later ones; neighbours outside the plane are ignored.
+// A neighbour that was not flagged has sums below every threshold, hence
+// below the cell's, and is beaten without being looked at.  The 8
+// neighbours' lookups (map entry, record, sums) are issued side by side.
+template <int LEVELS>
+__global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, const Group *__restrict__ groups,
+                                               const uint32_t *__restrict__ group_map, const float *__restrict__ sums,
+                                               uint32_t *__restrict__ cnt, uint32_t group_cap,
+                                               DevCand *__restrict__ cands, uint32_t cap) {
+    const int lane = threadIdx.x & 63;
+    const int i = lane & 15;
+    const uint32_t ng = min(cnt[CNT_GROUPS], group_cap);
+    const int64_t ngr = nb / SC_COLS;
+    const uint32_t stride = (gridDim.x * blockDim.x) >> 4;
+    // whole waves iterate together so that the appends stay wave-wide
+    for (uint32_t gb = ((blockIdx.x * blockDim.x) >> 4) + ((threadIdx.x & ~63u) >> 4); gb < ng; gb += stride) {
+        const uint32_t g = gb + (lane >> 4);
+        uint32_t lmask = 0;  // levels still alive
+        int64_t m = 0;
+        int iz = 0;
+        float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        if (g < ng) {
+            const Group r = groups[g];
+            const uint32_t cmask = r.iz_mask >> 16;
+            if ((cmask >> i) & 1u) {
+                iz = int(r.iz_mask & 0xffffu);
+                m = r.m;
+                const float *__restrict__ o = sums + int64_t(r.first + __popc(cmask & ((1u << i) - 1u))) * SUM_STRIDE;
 #pragma unroll
                 for (int l = 0; l <= LEVELS; ++l) {
-                    const bool beaten = earlier ? !(s[l] > s2[l]) : !(s[l] >= s2[l]);
-                    if (in && beaten) mask &= ~(1u << l);
+                    s[l] = o[l];
+                    if (s[l] >= thr.v[l]) lmask |= 1u << l;
                 }
             }
         }
+        if (lmask != 0) {
+            const int64_t k = m * SC_COLS + i;
+            // neighbour n = 3 (di + 1) + (dk + 1), n != 4
+            uint32_t gi[9];
+#pragma unroll
+            for (int n = 0; n < 9; ++n) {
+                const int di = n / 3 - 1, dk = n % 3 - 1;
+                gi[n] = ~0u;
+                if (n == 4) continue;
+                const int iz2 = iz + di;
+                const int64_t k2 = k + dk;
+                if (iz2 < 0 || iz2 >= nz || k2 < 0 || k2 >= nb) continue;
+                gi[n] = group_map[int64_t(iz2) * ngr + (k2 >> 4)];
+            }
+            Group rn[9];
+#pragma unroll
+            for (int n = 0; n < 9; ++n) {
+                rn[n] = Group{-1, 0u, 0u, 0u};
+                if (gi[n] < ng) rn[n] = groups[gi[n]];
+            }
+            float sn[9][5];
+            bool use[9];
+#pragma unroll
+            for (int n = 0; n < 9; ++n) {
+                const int di = n / 3 - 1, dk = n % 3 - 1;
+                const int64_t k2 = k + dk;
+                const int i2 = int(k2 & 15);
+                const uint32_t cm2 = rn[n].iz_mask >> 16;
+                use[n] = gi[n] < ng && int64_t(rn[n].m) == (k2 >> 4) &&
+                         (rn[n].iz_mask & 0xffffu) == uint32_t(iz + di) && ((cm2 >> i2) & 1u);
+#pragma unroll
+                for (int l = 0; l <= LEVELS; ++l) sn[n][l] = 0.f;
+                if (use[n]) {
+                    const float *__restrict__ o2 =
+                        sums + int64_t(rn[n].first + __popc(cm2 & ((1u << i2) - 1u))) * SUM_STRIDE;
+#pragma unroll
+                    for (int l = 0; l <= LEVELS; ++l) sn[n][l] = o2[l];
+                }
+            }
+#pragma unroll
+            for (int n = 0; n < 9; ++n) {
+                if (!use[n]) continue;
+                const bool earlier = n < 4;
+#pragma unroll
+                for (int l = 0; l <= LEVELS; ++l) {
+                    const bool beaten = earlier ? !(s[l] > sn[n][l]) : !(s[l] >= sn[n][l]);
+                    if (beaten) lmask &= ~(1u << l);
+                }
+            }
+        }
+        const int kk = int(m * SC_COLS + i);
 #pragma unroll
         for (int l = 0; l <= LEVELS; ++l) {
             bool taken;
-            const uint32_t slot = wave_append(valid && ((mask >> l) & 1u), count, lane, taken);
-            if (taken && slot < cap) cands[slot] = DevCand{k, iz, 1 << l, s[l]};
+            const uint32_t slot = wave_append((lmask >> l) & 1u, cnt + CNT_CANDS, lane, taken);
+            if (taken && slot < cap) cands[slot] = DevCand{kk, iz, 1 << l, s[l]};
         }
     }
 }
 
-// A hit list that overflowed makes the candidate list incomplete: raise a flag
+// Lists that overflowed make the candidate list incomplete: raise the flag
 // the host turns into OVERFLOW.
-__global__ void k_flag_hit_overflow(const uint32_t *__restrict__ hit_count, uint32_t hit_cap,
-                                    uint32_t *__restrict__ flag) {
-    if (threadIdx.x == 0 && *hit_count > hit_cap) *flag = 1u;
+__global__ void k_flag_overflow(uint32_t *__restrict__ cnt, uint32_t group_cap, uint32_t cell_cap) {
+    if (threadIdx.x == 0 && (cnt[CNT_GROUPS] > group_cap || cnt[CNT_CELLS] > cell_cap)) cnt[CNT_OVERFLOW] = 1u;
 }
 
 __global__ void k_zero_u32(uint32_t *__restrict__ p, int n) {
@@ -583,7 +773,8 @@ hipError_t launch_normalise(const float2 *X, const double *med, int W, int64_t n
 }
 
 hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, int tpb, int64_t nb,
-                            int log2s, int h, int64_t nseg, float *plane, hipStream_t st) {
+                            int log2s, int h, int64_t nseg, float *plane, uint8_t *codes, float code_inv,
+                            hipStream_t st) {
     if (nseg <= 0 || nz <= 0) return hipSuccess;
     if (tpb <= 0) return hipErrorInvalidValue;
     const int64_t nzb = (nz + tpb - 1) / tpb;
@@ -593,31 +784,44 @@ hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, i
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
 #define CALL(L)                                                                                       \
     hipLaunchKernelGGL((k_correlate<L>), dim3(unsigned(grid)), dim3(corr_threads(L)), 0, st, segspec, bank, \
-                       nz, tpb, nb, h, nseg, total, per, plane);
+                       nz, tpb, nb, h, nseg, total, per, plane, codes, code_inv);
     FDAS_SWITCH_LOG2(log2s, CALL)
 #undef CALL
     return hipGetLastError();
 }
 
-hipError_t launch_harmsum(const float *plane, int nz, int64_t nb, int izc, int nharm_max, const float *thr_host,
-                          void *hit_buf, uint32_t hit_cap, DevCand *cands, uint32_t *count, uint32_t cap,
-                          hipStream_t st) {
+size_t harmsum_scratch_bytes(int nz, int64_t nb, uint32_t cell_cap, uint32_t group_cap) {
+    return size_t(group_cap) * sizeof(Group) + size_t(cell_cap) * SUM_STRIDE * sizeof(float) +
+           size_t(nz) * size_t(nb / SC_COLS) * sizeof(uint32_t);
+}
+
+hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int64_t nb, int izc, int nharm_max,
+                          const float *thr_host, const uint32_t *code_thr, void *scratch, uint32_t cell_cap,
+                          uint32_t group_cap, DevCand *cands, uint32_t *count, uint32_t cap, hipStream_t st) {
     int levels = 0;
     while ((1 << levels) < nharm_max) ++levels;
     if ((1 << levels) != nharm_max || levels > 4) return hipErrorInvalidValue;
-    if (nb > (int64_t(1) << 26) || nb % (64 * HS_C) != 0 || nz > 65535) return hipErrorInvalidValue;
+    if (nb > (int64_t(1) << 26) || nb % SC_COLS != 0 || nz > 65535) return hipErrorInvalidValue;
     Thr thr{};
-    for (int l = 0; l <= levels; ++l) thr.v[l] = thr_host[l];
-    Hit *hits = static_cast<Hit *>(hit_buf);
-    uint32_t *hit_count = count + 1;  // the counter pair is zeroed by the caller
-    const int64_t cols = 64 * HS_C * HS_WAVES;
-    const dim3 grid1(unsigned((nb + cols - 1) / cols), unsigned((nz + HS_TZ - 1) / HS_TZ));
+    ScreenThr T{};
+    for (int l = 0; l <= levels; ++l) {
+        if (code_thr[l] > 0x8000u) return hipErrorInvalidValue;
+        thr.v[l] = thr_host[l];
+        T.k[l] = (0x8000u - code_thr[l]) * 0x10001u;
+    }
+    Group *groups = static_cast<Group *>(scratch);
+    float *sums = reinterpret_cast<float *>(groups + group_cap);
+    uint32_t *group_map = reinterpret_cast<uint32_t *>(sums + size_t(cell_cap) * SUM_STRIDE);
+    const int64_t cols = int64_t(SC_WAVE_COLS) * SC_WAVES;
+    const dim3 grid1(unsigned((nb + cols - 1) / cols), unsigned((nz + SC_TZ - 1) / SC_TZ));
     const unsigned grid2 = 2048;
-#define CALL(LV)                                                                                                \
-    hipLaunchKernelGGL((k_hits<LV>), grid1, dim3(64 * HS_WAVES), 0, st, plane, nz, nb, izc, thr, hits, hit_count, \
-                       hit_cap);                                                                               \
-    hipLaunchKernelGGL((k_peaks<LV>), dim3(grid2), dim3(256), 0, st, plane, nz, nb, izc, hits, hit_count, hit_cap,  \
-                       cands, count, cap);
+#define CALL(LV)                                                                                                   \
+    hipLaunchKernelGGL((k_screen<LV>), grid1, dim3(64 * SC_WAVES), 0, st, codes, nz, nb, izc, T, groups, group_map, \
+                       count, group_cap, cell_cap);                                                               \
+    hipLaunchKernelGGL((k_exact<LV>), dim3(grid2), dim3(256), 0, st, plane, nb, izc, groups, count, group_cap,      \
+                       sums);                                                                                     \
+    hipLaunchKernelGGL((k_peaks<LV>), dim3(grid2), dim3(256), 0, st, nz, nb, thr, groups, group_map, sums, count,   \
+                       group_cap, cands, cap);
     switch (levels) {
         case 0: CALL(0); break;
         case 1: CALL(1); break;
@@ -626,10 +830,8 @@ hipError_t launch_harmsum(const float *plane, int nz, int64_t nb, int izc, int n
         default: CALL(4); break;
     }
 #undef CALL
-    hipLaunchKernelGGL(k_flag_hit_overflow, dim3(1), dim3(64), 0, st, hit_count, hit_cap, count + 2);
+    hipLaunchKernelGGL(k_flag_overflow, dim3(1), dim3(64), 0, st, count, group_cap, cell_cap);
     return hipGetLastError();
 }
-
-size_t hit_record_bytes() { return sizeof(Hit); }
 
 }  // namespace fdas

@@ -46,22 +46,29 @@ hipError_t launch_normalise(const float2 *X, const double *med, int W, int64_t n
 
 // Fused correlation: for each segment s and template iz,
 //   y = IDFT_S(segspec[s] * bank[iz]) (unnormalised; bank carries 1/S),
-//   plane[iz][s L + n - h] = |y[n]|^2 for n in [h, S - h), inside [0, nb).
+//   plane[iz][s L + n - h] = |y[n]|^2 for n in [h, S - h), inside [0, nb),
+// and beside it the screening code plane (nz x nb bytes)
+//   codes[iz][k] = min(255, ceil(plane[iz][k] * code_inv)).
 hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, int tpb, int64_t nb,
-                            int log2s, int h, int64_t nseg, float *plane, hipStream_t st);
+                            int log2s, int h, int64_t nseg, float *plane, uint8_t *codes, float code_inv,
+                            hipStream_t st);
 
 // Harmonic sums over 1..nharm_max harmonics, thresholds and 3x3 local
-// maxima.  thr[i] is the threshold of 2^i harmonics.  Two passes: every
-// cell's sums with a list of the cells reaching any threshold (hit_buf, room
-// for hit_cap records of hit_record_bytes()), then the neighbour test for
-// every listed cell.  Appends to cands (capacity cap) through count[0]; the
-// hit list's counter is count[1]; count[2] is set to 1 if the hit list
-// overflowed (the candidates are then incomplete).  All three must start at
-// 0.  nb must be a multiple of 256, nz at most 65535.
-hipError_t launch_harmsum(const float *plane, int nz, int64_t nb, int izc, int nharm_max, const float *thr_host,
-                          void *hit_buf, uint32_t hit_cap, DevCand *cands, uint32_t *count, uint32_t cap,
-                          hipStream_t st);
-size_t hit_record_bytes();
+// maxima.  thr[i] is the threshold of 2^i harmonics, code_thr[i] (<= 0x8000)
+// the screen's threshold in code units: it must not exceed the code sum of any
+// cell whose exact FP32 sum reaches thr[i].  Three passes: a screen of every
+// cell's code sums that lists the cells which may reach a threshold, their
+// exact sums from the plane, and the threshold and neighbour tests on those.
+// scratch: harmsum_scratch_bytes(nz, nb, cell_cap, group_cap) bytes, for at
+// most cell_cap listed cells in group_cap groups of 16 columns.  count[0..3]
+// must start at 0: candidates are appended to cands (capacity cap) through
+// count[0]; count[1] and count[3] count listed cells and groups; count[2] is
+// set to 1 if either list overflowed (the candidates are then incomplete).
+// nb must be a multiple of 16, nz at most 65535.
+size_t harmsum_scratch_bytes(int nz, int64_t nb, uint32_t cell_cap, uint32_t group_cap);
+hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int64_t nb, int izc, int nharm_max,
+                          const float *thr_host, const uint32_t *code_thr, void *scratch, uint32_t cell_cap,
+                          uint32_t group_cap, DevCand *cands, uint32_t *count, uint32_t cap, hipStream_t st);
 
 // Candidate finishing: sort the first min(*count, cap) records by
 // (nharm, k, iz) and write public records (r, z, FP64 significance) to out.

@@ -82,7 +82,7 @@ namespace fdas {
 
 static int64_t buffer_bytes(const fdas_plan_s *core, int64_t nsamp) {
     const Geometry g = make_geometry(nsamp, core->S, core->h, core->W);
-    return series_bytes(g, core->S, core->nz) + nsamp * 4 + candidate_bytes(core->cand_cap);
+    return series_bytes(g, core->S, core->nz) + nsamp * 4 + candidate_bytes(core, g.nb);
 }
 
 static void free_buffers(Buffers *b) {
