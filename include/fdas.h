@@ -156,6 +156,12 @@ fdas_status fdas_search(fdas_plan_t *plan, int32_t in_kind, const void *in_dev,
 fdas_status fdas_plan_enable_timing(fdas_plan_t *plan, int32_t enable);
 fdas_status fdas_plan_stage_times(const fdas_plan_t *plan, double *ms_out, int64_t *nsearch_out);
 
+/* Work counts of the last fdas_search on this plan (diagnostics): out3[0]
+ * candidates found, out3[1] plane cells the harmonic-sum screen passed on to
+ * the exact FP32 sums, out3[2] groups of 16 columns holding those cells.
+ * INVAL if no search has completed on the plan. */
+fdas_status fdas_plan_search_counts(const fdas_plan_t *plan, int64_t *out3);
+
 /* Several float32 series, possibly of different power-of-two lengths
  * nsamp[i] <= the plan's nsamp, through the hot path on one stream with their
  * stages overlapped (no plane is returned).  Trial i's candidates go to

@@ -91,6 +91,7 @@ def load():
         "fdas_plan_fetch_spectrum": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp]),
         "fdas_plan_enable_timing": (_c_i32, [_c_vp, _c_i32]),
         "fdas_plan_stage_times": (_c_i32, [_c_vp, P(_c_dbl), P(_c_i64)]),
+        "fdas_plan_search_counts": (_c_i32, [_c_vp, P(_c_i64)]),
         "fdas_dft_c64": (_c_i32, [_c_i32, _c_i32, _c_i64, _c_vp, _c_vp, _c_vp]),
         "fdas_autotune": (_c_i32, [_c_vp, _c_i64, P(_Opts), ctypes.c_char_p, P(_c_i32), P(_c_i32),
                                    P(_c_dbl)]),
@@ -307,6 +308,13 @@ class Plan:
         n = ctypes.c_int64()
         _check(load().fdas_plan_stage_times(self._h, ms, ctypes.byref(n)))
         return dict(zip(self.STAGES, list(ms))), n.value
+
+    def search_counts(self):
+        """(candidates, cells passed by the harmonic-sum screen, their
+        16-column groups) of the last search."""
+        out = (ctypes.c_int64 * 3)()
+        _check(load().fdas_plan_search_counts(self._h, out))
+        return tuple(out)
 
     def close(self):
         if self._h:

@@ -148,7 +148,7 @@ extern "C" fdas_status fdas_search_batch(fdas_plan_t *plan, int32_t n, const flo
             first_err = hip_fail(plan, e, "batch trial launch");
             break;
         }
-        e = hipMemcpyAsync(ws.h_count, ws.count, 12, hipMemcpyDeviceToHost, plan->aux[slot]);
+        e = hipMemcpyAsync(ws.h_count, ws.count, 24, hipMemcpyDeviceToHost, plan->aux[slot]);
         if (e != hipSuccess) {
             first_err = hip_fail(plan, e, "copy candidate count");
             break;

@@ -131,7 +131,7 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
                          p->code_inv, st);
     if (e != hipSuccess) return hip_fail(p, e, "correlate");
     if ((e = mark(4)) != hipSuccess) return hip_fail(p, e, "timing event");
-    e = launch_zero_u32(dcount, 4, st);
+    e = launch_zero_u32(dcount, 6, st);
     if (e != hipSuccess) return hip_fail(p, e, "zero counter");
     e = launch_harmsum(plane, ws.codes, p->nz, g.nb, p->izc, p->opts.nharm_max, p->thr_f, p->code_thr, ws.hits,
                        p->hit_cap, p->group_cap, dcands, dcount, p->cand_cap, st);
@@ -236,7 +236,7 @@ void destroy_workspace(Workspace &ws) { free_workspace(ws); }
 // Candidates of a search enqueued on st: counter, then records, to the host.
 fdas_status collect(fdas_plan_s *p, Workspace &ws, fdas_cand *out, int64_t cap, int64_t *ncands,
                     hipStream_t st) {
-    hipError_t e = hipMemcpyAsync(ws.h_count, ws.count, 12, hipMemcpyDeviceToHost, st);
+    hipError_t e = hipMemcpyAsync(ws.h_count, ws.count, 24, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return hip_fail(p, e, "copy candidate count");
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(p, e, "search");
@@ -536,6 +536,22 @@ fdas_status fdas_plan_stage_times(const fdas_plan_t *plan, double *ms_out, int64
     }
     for (int i = 0; i < FDAS_NSTAGES; ++i) ms_out[i] = plan->stage_ms[size_t(i)];
     if (nsearch_out) *nsearch_out = plan->timed;
+    return FDAS_OK;
+}
+
+fdas_status fdas_plan_search_counts(const fdas_plan_t *plan, int64_t *out3) {
+    if (!plan || !out3) {
+        set_error("plan or output is NULL");
+        return FDAS_E_INVAL;
+    }
+    const uint32_t *c = plan->ws[0].h_count;
+    if (!c || !plan->last_X) {
+        set_error("no search has run on this plan");
+        return FDAS_E_INVAL;
+    }
+    out3[0] = c[0];
+    out3[1] = c[4];
+    out3[2] = c[5];
     return FDAS_OK;
 }
 

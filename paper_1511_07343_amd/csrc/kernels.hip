@@ -382,19 +382,6 @@ __device__ __forceinline__ void cell_sums(const float *__restrict__ P, int64_t n
     nested_sums<LEVELS>(v, s);
 }
 
-// Append the lanes with `pred` to a list through one atomic per wave.
-__device__ __forceinline__ uint32_t wave_append(bool pred, uint32_t *__restrict__ counter, int lane, bool &taken) {
-    const uint64_t mask = __ballot(pred);
-    taken = false;
-    if (!mask) return 0;
-    const int leader = __ffsll((long long)mask) - 1;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(counter, uint32_t(__popcll(mask)));
-    base = __shfl(base, leader);
-    taken = pred;
-    return base + uint32_t(__popcll(mask & ((uint64_t(1) << lane) - 1)));
-}
-
 // Pass 1, the screen: every cell's sums on the code plane (see power_code).
 // A cell's integer code sum is at least its power sum / delta, so a cell
 // whose code sums stay below T_l = floor(thr_l / delta (1 - 1e-5)) at every
@@ -430,9 +417,12 @@ struct Group {
     uint32_t pad;
 };
 
-// Counters (zeroed before the pass): candidates, flagged cells, overflow
-// flag, groups.
-enum { CNT_CANDS = 0, CNT_CELLS = 1, CNT_OVERFLOW = 2, CNT_GROUPS = 3 };
+// Counters (six 32-bit words, zeroed before the pass): candidates; overflow
+// flag; flagged cells (low word) and groups (high word) of one 64-bit counter,
+// so that a wave reserves both with one atomic.
+enum { CNT_CANDS = 0, CNT_OVERFLOW = 2, CNT_PAIR = 4 };
+
+__device__ __forceinline__ uint32_t group_count(const uint32_t *cnt) { return cnt[CNT_PAIR + 1]; }
 
 // Byte layout of one fraction's 16 codes.
 template <int J>
@@ -492,16 +482,24 @@ __global__ __launch_bounds__(64 * SC_WAVES) void k_screen(const uint8_t *__restr
                                                           int izc, ScreenThr T, Group *__restrict__ groups,
                                                           uint32_t *__restrict__ group_map, uint32_t *__restrict__ cnt,
                                                           uint32_t group_cap, uint32_t cell_cap) {
+    // Row masks of the wave, kept until its records are written.
+    __shared__ uint32_t rowmask_lds[SC_WAVES][SC_TZ][64];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    // a workgroup covers SC_WAVES * 1024 columns and SC_TZ rows
     const int64_t m = (int64_t(blockIdx.x) * SC_WAVES + wave) * 64 + lane;  // column group
+    const int iz0 = blockIdx.y * SC_TZ;
     const int64_t ngr = nb / SC_COLS;
     const bool valid = m < ngr;
-    if (!__any(valid)) return;
+    if (!__any(valid) || iz0 >= nz) return;
     const int64_t mm = valid ? m : 0;  // lanes past the end read group 0 and report nothing
-    const int iz0 = blockIdx.y * SC_TZ;
-    const int iz1 = min(nz, iz0 + SC_TZ);
-    for (int iz = iz0; iz < iz1; ++iz) {
+    uint32_t *__restrict__ rowmask = &rowmask_lds[wave][0][lane];  // row r at rowmask[64 r]
+    uint32_t mycells = 0, mygroups = 0;
+#pragma unroll 1
+    for (int r = 0; r < SC_TZ; ++r) {
+        const int iz = iz0 + r;
+        rowmask[64 * r] = 0;
+        if (iz >= nz) continue;
         const int d = iz - izc;
         uint32_t G[LEVELS + 1][8];
 #pragma unroll
@@ -527,43 +525,70 @@ __global__ __launch_bounds__(64 * SC_WAVES) void k_screen(const uint8_t *__restr
             mask |= (fl >> 31) << (2 * p + 1);
         }
         if (!valid) mask = 0;
-        if (!__any(mask != 0)) continue;
-        // one group record per lane with flagged cells; their cells get
-        // consecutive indices
+        rowmask[64 * r] = mask;
+        mycells += __popc(mask);
+        mygroups += mask != 0 ? 1u : 0u;
+    }
+    // One group record per (lane, row) with flagged cells; a lane's records
+    // and cells get consecutive indices.  One atomic per wave reserves both
+    // lists; crossing a capacity raises the overflow flag at once (so a count
+    // that later wraps cannot hide it).  (Each lane reads back only its own
+    // LDS words, so no barrier is needed.)
+    if (!__any(mycells != 0)) return;
+    // cells (<= 16 SC_TZ 64) in the low half, groups in the high half
+    const uint32_t incl = wave_scan((mygroups << 16) | mycells, lane);
+    const uint32_t total = __shfl(incl, 63);
+    uint32_t cbase = 0, gbase = 0;
+    if (lane == 0) {
+        const uint32_t tc = total & 0xffffu, tg = total >> 16;
+        const unsigned long long old = atomicAdd(reinterpret_cast<unsigned long long *>(cnt + CNT_PAIR),
+                                                 (static_cast<unsigned long long>(tg) << 32) | tc);
+        cbase = uint32_t(old);
+        gbase = uint32_t(old >> 32);
+        if (uint64_t(cbase) + tc > cell_cap || uint64_t(gbase) + tg > group_cap) cnt[CNT_OVERFLOW] = 1u;
+    }
+    uint32_t first = __shfl(cbase, 0) + (incl & 0xffffu) - mycells;
+    uint32_t g = __shfl(gbase, 0) + (incl >> 16) - mygroups;
+#pragma unroll 1
+    for (int r = 0; r < SC_TZ; ++r) {
+        const uint32_t mask = rowmask[64 * r];
+        if (mask == 0) continue;
         const uint32_t ncell = __popc(mask);
-        const uint32_t incl = wave_scan(ncell, lane);
-        const uint32_t total = __shfl(incl, 63);
-        uint32_t cbase = 0;
-        if (lane == 0) cbase = atomicAdd(cnt + CNT_CELLS, total);
-        cbase = __shfl(cbase, 0);
-        bool taken;
-        const uint32_t g = wave_append(mask != 0, cnt + CNT_GROUPS, lane, taken);
-        const uint32_t first = cbase + incl - ncell;
         // every record below min(count, group_cap) is written, with no cells
         // when they do not fit (the overflow flag reports the loss)
-        if (taken && g < group_cap) {
+        if (g < group_cap) {
             const bool fits = uint64_t(first) + ncell <= cell_cap;
+            const int iz = iz0 + r;
             groups[g] = Group{int32_t(m), uint32_t(iz) | ((fits ? mask : 0u) << 16), first, 0u};
             if (fits) group_map[int64_t(iz) * ngr + m] = g;
         }
+        ++g;
+        first += ncell;
     }
 }
 
 constexpr int SUM_STRIDE = 5;  // floats per flagged cell in the sums array
 
+// A record below the group count was written by this search; the range test
+// only guards against counts that wrapped after an overflow.
+__device__ __forceinline__ bool group_ok(const Group &r, int nz, int64_t nb, uint32_t cell_cap) {
+    return r.m >= 0 && int64_t(r.m) < nb / SC_COLS && int(r.iz_mask & 0xffffu) < nz &&
+           uint64_t(r.first) + uint32_t(__popc(r.iz_mask >> 16)) <= cell_cap;
+}
+
 // Pass 2: the exact FP32 sums of every flagged cell (16 lanes per group,
 // lane i on column 16 m + i), loaded from the plane in the one summation
 // order of nested_sums.
 template <int LEVELS>
-__global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int64_t nb, int izc,
+__global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int nz, int64_t nb, int izc,
                                                const Group *__restrict__ groups, const uint32_t *__restrict__ cnt,
-                                               uint32_t group_cap, float *__restrict__ sums) {
-    const uint32_t ng = min(cnt[CNT_GROUPS], group_cap);
+                                               uint32_t group_cap, uint32_t cell_cap, float *__restrict__ sums) {
+    const uint32_t ng = min(group_count(cnt), group_cap);
     const int i = threadIdx.x & 15;
     for (uint32_t g = (blockIdx.x * blockDim.x + threadIdx.x) >> 4; g < ng; g += (gridDim.x * blockDim.x) >> 4) {
         const Group r = groups[g];
         const uint32_t mask = r.iz_mask >> 16;
-        if (!((mask >> i) & 1u)) continue;
+        if (!((mask >> i) & 1u) || !group_ok(r, nz, nb, cell_cap)) continue;
         float s[5];
         cell_sums<LEVELS>(P, nb, izc, int(r.iz_mask & 0xffffu), r.m * SC_COLS + i, s);
         float *__restrict__ o = sums + int64_t(r.first + __popc(mask & ((1u << i) - 1u))) * SUM_STRIDE;
@@ -582,16 +607,20 @@ __global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int6
 template <int LEVELS>
 __global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, const Group *__restrict__ groups,
                                                const uint32_t *__restrict__ group_map, const float *__restrict__ sums,
-                                               uint32_t *__restrict__ cnt, uint32_t group_cap,
+                                               uint32_t *__restrict__ cnt, uint32_t group_cap, uint32_t cell_cap,
                                                DevCand *__restrict__ cands, uint32_t cap) {
+    __shared__ uint32_t wsum[2][4];  // per-wave candidate counts, by iteration parity
+    __shared__ uint32_t wgbase[2];
     const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     const int i = lane & 15;
-    const uint32_t ng = min(cnt[CNT_GROUPS], group_cap);
+    const uint32_t ng = min(group_count(cnt), group_cap);
     const int64_t ngr = nb / SC_COLS;
-    const uint32_t stride = (gridDim.x * blockDim.x) >> 4;
-    // whole waves iterate together so that the appends stay wave-wide
-    for (uint32_t gb = ((blockIdx.x * blockDim.x) >> 4) + ((threadIdx.x & ~63u) >> 4); gb < ng; gb += stride) {
-        const uint32_t g = gb + (lane >> 4);
+    // the workgroup iterates as a whole (16 groups per step) so that one
+    // atomic per step reserves the slots of all its candidates
+    int par = 0;
+    for (uint32_t gw = blockIdx.x * 16u; gw < ng; gw += gridDim.x * 16u, par ^= 1) {
+        const uint32_t g = gw + uint32_t(threadIdx.x >> 4);
         uint32_t lmask = 0;  // levels still alive
         int64_t m = 0;
         int iz = 0;
@@ -599,7 +628,7 @@ __global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, cons
         if (g < ng) {
             const Group r = groups[g];
             const uint32_t cmask = r.iz_mask >> 16;
-            if ((cmask >> i) & 1u) {
+            if (((cmask >> i) & 1u) && group_ok(r, nz, nb, cell_cap)) {
                 iz = int(r.iz_mask & 0xffffu);
                 m = r.m;
                 const float *__restrict__ o = sums + int64_t(r.first + __popc(cmask & ((1u << i) - 1u))) * SUM_STRIDE;
@@ -639,7 +668,8 @@ __global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, cons
                 const int i2 = int(k2 & 15);
                 const uint32_t cm2 = rn[n].iz_mask >> 16;
                 use[n] = gi[n] < ng && int64_t(rn[n].m) == (k2 >> 4) &&
-                         (rn[n].iz_mask & 0xffffu) == uint32_t(iz + di) && ((cm2 >> i2) & 1u);
+                         (rn[n].iz_mask & 0xffffu) == uint32_t(iz + di) && ((cm2 >> i2) & 1u) &&
+                         uint64_t(rn[n].first) + uint32_t(__popc(cm2)) <= cell_cap;
 #pragma unroll
                 for (int l = 0; l <= LEVELS; ++l) sn[n][l] = 0.f;
                 if (use[n]) {
@@ -660,20 +690,26 @@ __global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, cons
                 }
             }
         }
+        const uint32_t nc = __popc(lmask);
+        const uint32_t incl = wave_scan(nc, lane);
+        if (lane == 63) wsum[par][wave] = incl;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const uint32_t tot = wsum[par][0] + wsum[par][1] + wsum[par][2] + wsum[par][3];
+            wgbase[par] = tot ? atomicAdd(cnt + CNT_CANDS, tot) : 0u;
+        }
+        __syncthreads();
+        uint32_t slot = wgbase[par] + incl - nc;
+        for (int w = 0; w < wave; ++w) slot += wsum[par][w];
         const int kk = int(m * SC_COLS + i);
 #pragma unroll
         for (int l = 0; l <= LEVELS; ++l) {
-            bool taken;
-            const uint32_t slot = wave_append((lmask >> l) & 1u, cnt + CNT_CANDS, lane, taken);
-            if (taken && slot < cap) cands[slot] = DevCand{kk, iz, 1 << l, s[l]};
+            if ((lmask >> l) & 1u) {
+                if (slot < cap) cands[slot] = DevCand{kk, iz, 1 << l, s[l]};
+                ++slot;
+            }
         }
     }
-}
-
-// Lists that overflowed make the candidate list incomplete: raise the flag
-// the host turns into OVERFLOW.
-__global__ void k_flag_overflow(uint32_t *__restrict__ cnt, uint32_t group_cap, uint32_t cell_cap) {
-    if (threadIdx.x == 0 && (cnt[CNT_GROUPS] > group_cap || cnt[CNT_CELLS] > cell_cap)) cnt[CNT_OVERFLOW] = 1u;
 }
 
 __global__ void k_zero_u32(uint32_t *__restrict__ p, int n) {
@@ -812,16 +848,16 @@ hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int6
     Group *groups = static_cast<Group *>(scratch);
     float *sums = reinterpret_cast<float *>(groups + group_cap);
     uint32_t *group_map = reinterpret_cast<uint32_t *>(sums + size_t(cell_cap) * SUM_STRIDE);
-    const int64_t cols = int64_t(SC_WAVE_COLS) * SC_WAVES;
-    const dim3 grid1(unsigned((nb + cols - 1) / cols), unsigned((nz + SC_TZ - 1) / SC_TZ));
+    const int64_t rows = SC_TZ, cols = int64_t(SC_WAVE_COLS) * SC_WAVES;
+    const dim3 grid1(unsigned((nb + cols - 1) / cols), unsigned((nz + rows - 1) / rows));
     const unsigned grid2 = 2048;
 #define CALL(LV)                                                                                                   \
     hipLaunchKernelGGL((k_screen<LV>), grid1, dim3(64 * SC_WAVES), 0, st, codes, nz, nb, izc, T, groups, group_map, \
                        count, group_cap, cell_cap);                                                               \
-    hipLaunchKernelGGL((k_exact<LV>), dim3(grid2), dim3(256), 0, st, plane, nb, izc, groups, count, group_cap,      \
-                       sums);                                                                                     \
+    hipLaunchKernelGGL((k_exact<LV>), dim3(grid2), dim3(256), 0, st, plane, nz, nb, izc, groups, count, group_cap,  \
+                       cell_cap, sums);                                                                           \
     hipLaunchKernelGGL((k_peaks<LV>), dim3(grid2), dim3(256), 0, st, nz, nb, thr, groups, group_map, sums, count,   \
-                       group_cap, cands, cap);
+                       group_cap, cell_cap, cands, cap);
     switch (levels) {
         case 0: CALL(0); break;
         case 1: CALL(1); break;
@@ -830,7 +866,6 @@ hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int6
         default: CALL(4); break;
     }
 #undef CALL
-    hipLaunchKernelGGL(k_flag_overflow, dim3(1), dim3(64), 0, st, count, group_cap, cell_cap);
     return hipGetLastError();
 }
 

@@ -60,9 +60,9 @@ hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, i
 // cell's code sums that lists the cells which may reach a threshold, their
 // exact sums from the plane, and the threshold and neighbour tests on those.
 // scratch: harmsum_scratch_bytes(nz, nb, cell_cap, group_cap) bytes, for at
-// most cell_cap listed cells in group_cap groups of 16 columns.  count[0..3]
+// most cell_cap listed cells in group_cap groups of 16 columns.  count[0..5]
 // must start at 0: candidates are appended to cands (capacity cap) through
-// count[0]; count[1] and count[3] count listed cells and groups; count[2] is
+// count[0]; count[4] and count[5] count listed cells and groups; count[2] is
 // set to 1 if either list overflowed (the candidates are then incomplete).
 // nb must be a multiple of 16, nz at most 65535.
 size_t harmsum_scratch_bytes(int nz, int64_t nb, uint32_t cell_cap, uint32_t group_cap);

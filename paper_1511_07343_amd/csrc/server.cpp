@@ -203,7 +203,7 @@ static void scheduler(fdas_server_s *sv) {
                 const Geometry g = make_geometry(req.nsamp, sv->core->S, sv->core->h, sv->core->W);
                 s = enqueue_search(sv->core, buf->ws, g, FDAS_IN_SERIES_F32, buf->series, buf->ws.plane,
                                    buf->ws.cands, buf->ws.count, st);
-                if (s == FDAS_OK) e = hipMemcpyAsync(buf->ws.h_count, buf->ws.count, 12, hipMemcpyDeviceToHost, st);
+                if (s == FDAS_OK) e = hipMemcpyAsync(buf->ws.h_count, buf->ws.count, 24, hipMemcpyDeviceToHost, st);
             }
             if (e == hipSuccess && s == FDAS_OK) e = hipEventRecord(free_slot->done, st);
             if (e != hipSuccess || s != FDAS_OK) {
