@@ -23,18 +23,58 @@ __device__ __forceinline__ uint32_t clamp_count(const uint32_t *count, uint32_t 
     return c < cap ? c : cap;
 }
 
-// key = level << 40 | k << 14 | iz, level = log2(nharm): ascending keys are
-// ascending (nharm, k, iz).
+// key = (level << (bk + bz)) | (k << bz) | iz, level = log2(nharm), with k
+// in bk bits and iz in bz bits: ascending keys are ascending (nharm, k, iz).
 __global__ __launch_bounds__(256) void k_cand_keys(const DevCand *__restrict__ dc, const uint32_t *__restrict__ count,
-                                                   uint32_t cap, uint64_t *__restrict__ keys,
+                                                   uint32_t cap, int bk, int bz, uint64_t *__restrict__ keys,
                                                    uint32_t *__restrict__ vals) {
     const uint32_t n = clamp_count(count, cap);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const DevCand c = dc[i];
         const uint64_t level = uint64_t(31 - __clz(c.nharm));
-        keys[i] = (level << 40) | (uint64_t(uint32_t(c.k)) << 14) | uint64_t(uint32_t(c.iz));
+        keys[i] = (level << (bk + bz)) | (uint64_t(uint32_t(c.k)) << bz) | uint64_t(uint32_t(c.iz));
         vals[i] = i;
     }
+}
+
+// Lists of at most SMALL records are sorted by one workgroup in LDS
+// (bitonic, not stable, which is harmless: no two records share a key); the
+// radix passes skip them.
+constexpr uint32_t SMALL = 2048;
+constexpr int SMALL_THREADS = 1024;
+
+__global__ __launch_bounds__(SMALL_THREADS) void k_small_sort(const uint64_t *__restrict__ kin,
+                                                              const uint32_t *__restrict__ vin,
+                                                              const uint32_t *__restrict__ count, uint32_t cap,
+                                                              uint32_t *__restrict__ vout) {
+    __shared__ uint64_t key[SMALL];
+    __shared__ uint32_t val[SMALL];
+    const uint32_t n = clamp_count(count, cap);
+    if (n > SMALL) return;
+    const int t = threadIdx.x;
+    for (uint32_t i = t; i < SMALL; i += SMALL_THREADS) {
+        key[i] = i < n ? kin[i] : ~uint64_t(0);
+        val[i] = i < n ? vin[i] : 0u;
+    }
+    for (uint32_t size = 2; size <= SMALL; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            __syncthreads();
+            for (uint32_t i = t; i < SMALL / 2; i += SMALL_THREADS) {
+                const uint32_t lo = 2 * stride * (i / stride) + (i % stride), hi = lo + stride;
+                const bool asc = (lo & size) == 0;
+                const uint64_t a = key[lo], b = key[hi];
+                if ((a > b) == asc) {
+                    key[lo] = b;
+                    key[hi] = a;
+                    const uint32_t v = val[lo];
+                    val[lo] = val[hi];
+                    val[hi] = v;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < n; i += SMALL_THREADS) vout[i] = val[i];
 }
 
 __device__ __forceinline__ void block_range(uint32_t n, uint32_t &beg, uint32_t &end) {
@@ -48,42 +88,59 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *__restri
                                                         const uint32_t *__restrict__ count, uint32_t cap,
                                                         int shift, uint32_t *__restrict__ hist) {
     __shared__ uint32_t lh[RS_DIGITS];
+    const uint32_t n = clamp_count(count, cap);
+    if (n <= SMALL) return;
     const int t = threadIdx.x;
     lh[t] = 0;
     __syncthreads();
     uint32_t beg, end;
-    block_range(clamp_count(count, cap), beg, end);
+    block_range(n, beg, end);
     for (uint32_t i = beg + t; i < end; i += RS_THREADS) atomicAdd(&lh[(keys[i] >> shift) & 255u], 1u);
     __syncthreads();
     hist[t * RS_BLOCKS + blockIdx.x] = lh[t];
 }
 
-// Exclusive scan of the RS_DIGITS * RS_BLOCKS counts (one workgroup).
+// Exclusive scan of the RS_DIGITS * RS_BLOCKS counts (one workgroup): each
+// thread owns 64 consecutive counts, a wave scans its threads' totals with
+// shuffles and one LDS step joins the waves.
 constexpr int SCAN_THREADS = 1024;
 constexpr int SCAN_PER = RS_DIGITS * RS_BLOCKS / SCAN_THREADS;
-__global__ __launch_bounds__(SCAN_THREADS) void k_rs_scan(uint32_t *__restrict__ hist) {
-    __shared__ uint32_t part[SCAN_THREADS];
-    const int t = threadIdx.x;
-    uint32_t loc[SCAN_PER];
+static_assert(SCAN_PER % 4 == 0, "vector loads of the counts");
+__global__ __launch_bounds__(SCAN_THREADS) void k_rs_scan(uint32_t *__restrict__ hist,
+                                                          const uint32_t *__restrict__ count, uint32_t cap) {
+    __shared__ uint32_t wtot[SCAN_THREADS / 64];
+    if (clamp_count(count, cap) <= SMALL) return;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint4 *__restrict__ h4 = reinterpret_cast<uint4 *>(hist) + t * (SCAN_PER / 4);
+    uint4 loc[SCAN_PER / 4];
     uint32_t sum = 0;
 #pragma unroll
-    for (int i = 0; i < SCAN_PER; ++i) {
-        loc[i] = hist[t * SCAN_PER + i];
-        sum += loc[i];
+    for (int q = 0; q < SCAN_PER / 4; ++q) {
+        loc[q] = h4[q];
+        sum += loc[q].x + loc[q].y + loc[q].z + loc[q].w;
     }
-    part[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < SCAN_THREADS; off <<= 1) {  // Hillis-Steele inclusive scan
-        const uint32_t v = t >= off ? part[t - off] : 0u;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    uint32_t run = part[t] - sum;
+    uint32_t incl = sum;
 #pragma unroll
-    for (int i = 0; i < SCAN_PER; ++i) {
-        hist[t * SCAN_PER + i] = run;
-        run += loc[i];
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
+    }
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (int w = 0; w < wave; ++w) run += wtot[w];
+#pragma unroll
+    for (int q = 0; q < SCAN_PER / 4; ++q) {
+        uint4 o;
+        o.x = run;
+        run += loc[q].x;
+        o.y = run;
+        run += loc[q].y;
+        o.z = run;
+        run += loc[q].z;
+        o.w = run;
+        run += loc[q].w;
+        h4[q] = o;
     }
 }
 
@@ -99,10 +156,12 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *__res
                                                            uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
     __shared__ uint32_t base[RS_DIGITS];
     __shared__ uint32_t cnt[RS_THREADS / 64][RS_DIGITS];
+    const uint32_t n = clamp_count(count, cap);
+    if (n <= SMALL) return;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     base[t] = hist[t * RS_BLOCKS + blockIdx.x];
     uint32_t beg, end;
-    block_range(clamp_count(count, cap), beg, end);
+    block_range(n, beg, end);
     const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
     for (uint32_t tile = beg; tile < end; tile += RS_THREADS) {
 #pragma unroll
@@ -171,17 +230,33 @@ __device__ double log_normal_tail_d(double sg) {
     return -0.5 * sg * sg - log(sg) - 0.91893853320467274178 + log(series);
 }
 
-// sigma with Phi_c(sigma) = Q(n, power), by bisection.
+// sigma with Phi_c(sigma) = Q(n, power): Newton's method on
+// f(sigma) = log Phi_c(sigma) - log Q, with f' = -phi(sigma) / Phi_c(sigma)
+// (f is decreasing and concave), inside a bracket that falls back to
+// bisection whenever a Newton step leaves it.
 __device__ double significance_d(double power, int n) {
     const double target = log_gamma_survival_d(n, power);
     double lo = -40.0, hi = 40.0;
     if (log_normal_tail_d(lo) < target) return lo;
     while (log_normal_tail_d(hi) > target && hi < 1e9) hi *= 2.0;
-    for (int it = 0; it < 200 && hi - lo > 1e-12 * fmax(1.0, fabs(hi)); ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (log_normal_tail_d(mid) > target) lo = mid; else hi = mid;
+    // start from the tail asymptote log Phi_c(x) ~ -x^2/2 - log(x sqrt(2 pi))
+    double x = sqrt(fmax(-2.0 * target, 1.0));
+    x = fmin(fmax(x, lo), hi);
+    for (int it = 0; it < 100; ++it) {
+        const double lt = log_normal_tail_d(x);
+        const double f = lt - target;
+        if (f > 0.0) lo = x; else hi = x;
+        const double dlog = -exp(-0.5 * x * x - 0.91893853320467274178 - lt);  // d/dx log Phi_c
+        double nx = x - f / dlog;
+        if (fabs(nx - x) <= 1e-12 * fmax(1.0, fabs(x))) {
+            x = nx;
+            break;
+        }
+        if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
+        x = nx;
+        if (hi - lo <= 1e-12 * fmax(1.0, fabs(hi))) break;
     }
-    return 0.5 * (lo + hi);
+    return x;
 }
 
 __global__ __launch_bounds__(256) void k_cand_finalize(const DevCand *__restrict__ dc,
@@ -205,27 +280,36 @@ __global__ __launch_bounds__(256) void k_cand_finalize(const DevCand *__restrict
 
 }  // namespace
 
+// Layout: keys k0, k1 (cap each), values v0, v1 (cap each), then the digit
+// counts at the next 16-byte boundary.
 size_t cand_sort_scratch_bytes(uint32_t cap) {
-    return size_t(cap) * (2 * sizeof(uint64_t) + 2 * sizeof(uint32_t)) + size_t(RS_DIGITS) * RS_BLOCKS * 4;
+    return size_t(cap) * (2 * sizeof(uint64_t) + 2 * sizeof(uint32_t)) + 16 + size_t(RS_DIGITS) * RS_BLOCKS * 4;
 }
 
-hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch,
-                                    double zmax, double dz, fdas_cand *out, hipStream_t st) {
+hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch, int nz,
+                                    int64_t nb, double zmax, double dz, fdas_cand *out, hipStream_t st) {
     if (cap == 0) return hipSuccess;
+    int bk = 1, bz = 1;
+    while ((int64_t(1) << bk) < nb) ++bk;
+    while ((1 << bz) < nz) ++bz;
+    const int passes = (3 + bk + bz + 7) / 8;
     uint64_t *k0 = static_cast<uint64_t *>(scratch);
     uint64_t *k1 = k0 + cap;
     uint32_t *v0 = reinterpret_cast<uint32_t *>(k1 + cap);
     uint32_t *v1 = v0 + cap;
-    uint32_t *hist = v1 + cap;
+    uint32_t *hist = reinterpret_cast<uint32_t *>((reinterpret_cast<uintptr_t>(v1 + cap) + 15) & ~uintptr_t(15));
     const uint64_t blocks = (uint64_t(cap) + 255) / 256;
     const unsigned grid = unsigned(blocks < 1024 ? blocks : 1024);
-    hipLaunchKernelGGL(k_cand_keys, dim3(grid), dim3(256), 0, st, dc, count, cap, k0, v0);
+    hipLaunchKernelGGL(k_cand_keys, dim3(grid), dim3(256), 0, st, dc, count, cap, bk, bz, k0, v0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // 43 key bits (3 level, 26 k, 14 iz): six 8-bit passes, ending in k0/v0
-    for (int shift = 0; shift < 48; shift += 8) {
+    // the order ends in v0 after an even number of passes, else in v1
+    hipLaunchKernelGGL(k_small_sort, dim3(1), dim3(SMALL_THREADS), 0, st, k0, v0, count, cap,
+                       (passes % 2) ? v1 : v0);
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
         hipLaunchKernelGGL(k_rs_hist, dim3(RS_BLOCKS), dim3(RS_THREADS), 0, st, k0, count, cap, shift, hist);
-        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(SCAN_THREADS), 0, st, hist);
+        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(SCAN_THREADS), 0, st, hist, count, cap);
         hipLaunchKernelGGL(k_rs_scatter, dim3(RS_BLOCKS), dim3(RS_THREADS), 0, st, k0, v0, count, cap, shift, hist, k1,
                            v1);
         e = hipGetLastError();

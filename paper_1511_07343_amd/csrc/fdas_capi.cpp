@@ -136,7 +136,7 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
     e = launch_harmsum(plane, ws.codes, p->nz, g.nb, p->izc, p->opts.nharm_max, p->thr_f, p->code_thr, ws.hits,
                        p->hit_cap, p->group_cap, dcands, dcount, p->cand_cap, st);
     if (e != hipSuccess) return hip_fail(p, e, "harmonic sum");
-    e = launch_finish_candidates(dcands, dcount, p->cand_cap, ws.sort, p->zmax, p->dz, ws.final, st);
+    e = launch_finish_candidates(dcands, dcount, p->cand_cap, ws.sort, p->nz, g.nb, p->zmax, p->dz, ws.final, st);
     if (e != hipSuccess) return hip_fail(p, e, "candidate sort");
     if ((e = mark(5)) != hipSuccess) return hip_fail(p, e, "timing event");
     p->last_X = X;

@@ -71,10 +71,11 @@ hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int6
                           uint32_t group_cap, DevCand *cands, uint32_t *count, uint32_t cap, hipStream_t st);
 
 // Candidate finishing: sort the first min(*count, cap) records by
-// (nharm, k, iz) and write public records (r, z, FP64 significance) to out.
+// (nharm, k, iz) (k < nb, iz < nz) and write public records (r, z, FP64
+// significance) to out.
 // scratch: cand_sort_scratch_bytes(cap) bytes.
 size_t cand_sort_scratch_bytes(uint32_t cap);
-hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch,
-                                    double zmax, double dz, fdas_cand *out, hipStream_t st);
+hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch, int nz,
+                                    int64_t nb, double zmax, double dz, fdas_cand *out, hipStream_t st);
 
 }  // namespace fdas
