@@ -79,8 +79,17 @@ typedef struct fdas_opts {
     int32_t median_window;       /* normalisation block length W, 32..8192, pow2 (def. 1024) */
     int64_t cand_capacity;       /* device candidate buffer entries (default 1<<20)          */
     int32_t templates_per_block; /* templates per correlation workgroup, 0 = automatic       */
-    int32_t reserved;
+    int32_t correlator;          /* FDAS_CORR_FFT_F32 (default) or a matrix form, see below   */
 } fdas_opts;
+
+/* Correlator of a plan.  FDAS_CORR_FFT_F32: overlap-save segments, FP32 DFTs
+ * (Sec. 2, Sec. 4 steps 3-7).  FDAS_CORR_GEMM_BF16 / FDAS_CORR_GEMM_F16:
+ * Eq. (1) summed directly as one real matrix product on the matrix cores
+ * with BF16 / FP16 operands (spectrum and taps rounded to nearest) and FP32
+ * accumulation; the segment length is then unused, and the half-width h must
+ * be at most 271 (zmax <= 510) or fdas_plan returns INVAL.  A precision
+ * variant: its powers carry the 16-bit rounding of the operands. */
+enum { FDAS_CORR_FFT_F32 = 0, FDAS_CORR_GEMM_BF16 = 1, FDAS_CORR_GEMM_F16 = 2 };
 
 void fdas_default_opts(fdas_opts *opts);
 

@@ -40,7 +40,7 @@ class _Cand(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("nharm_max", ctypes.c_int32),
                 ("median_window", ctypes.c_int32), ("cand_capacity", ctypes.c_int64),
-                ("templates_per_block", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("templates_per_block", ctypes.c_int32), ("correlator", ctypes.c_int32)]
 
 
 CAND_DTYPE = np.dtype([("k", "<i8"), ("iz", "<i4"), ("nharm", "<i4"), ("r", "<f8"), ("z", "<f8"),
@@ -127,7 +127,12 @@ def _stream_handle(stream=None):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=0, templates_per_block=0):
+# Correlators (fdas_opts.correlator): FP32 overlap-save FFTs, or Eq. (1) as a
+# matrix product with BF16 / FP16 operands and FP32 accumulation.
+CORRELATORS = {"fft": 0, "bf16": 1, "f16": 2}
+
+
+def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=0, templates_per_block=0, correlator="fft"):
     o = _Opts()
     load().fdas_default_opts(ctypes.byref(o))
     o.sigma = float(sigma)
@@ -135,6 +140,9 @@ def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=0, template
     o.median_window = int(median_window)
     o.cand_capacity = int(cand_capacity)
     o.templates_per_block = int(templates_per_block)
+    if correlator not in CORRELATORS:
+        raise ValueError(f"correlator must be one of {sorted(CORRELATORS)}")
+    o.correlator = CORRELATORS[correlator]
     return o
 
 

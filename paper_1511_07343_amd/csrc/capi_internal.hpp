@@ -36,6 +36,7 @@ struct Workspace {
     float2 *seg = nullptr;   // segment spectra, nseg x S
     float *plane = nullptr;  // f-fdot plane, nz x nb
     uint8_t *codes = nullptr;  // screening codes of the plane, nz x nb
+    uint32_t *xl = nullptr;    // 16-bit spectrum of the matrix correlator, nb words
     DevCand *cands = nullptr;     // unordered records from the harmonic-sum kernel
     uint32_t *count = nullptr;    // their count (may exceed the capacity)
     void *hits = nullptr;         // harmonic-sum screen lists, exact sums and group map
@@ -60,7 +61,10 @@ struct fdas_plan_s {
     float thr_f[5] = {};
     float code_inv = 1.f;       // 1 / delta of the screening codes
     uint32_t code_thr[5] = {};  // screen thresholds in code units
-    float2 *d_bank = nullptr;  // nz x S, segment domain, scaled by 1/S
+    float2 *d_bank = nullptr;  // nz x S, segment domain, scaled by 1/S (FFT correlator)
+    void *d_gemm = nullptr;    // template matrix of the matrix correlator
+    int32_t corr = 0;          // FDAS_CORR_*
+    int num_cu = 256;          // compute units of the device (matrix correlator grid)
     std::array<fdas::Workspace, 2> ws{};
     std::array<hipStream_t, 2> aux{};
     std::array<hipEvent_t, 4> events{};

@@ -43,6 +43,10 @@ fdas_status validate_opts(const fdas_opts &o) {
         set_error("opts.nharm_max must be 1, 2, 4, 8 or 16");
         return FDAS_E_INVAL;
     }
+    if (o.correlator < FDAS_CORR_FFT_F32 || o.correlator > FDAS_CORR_GEMM_F16) {
+        set_error("opts.correlator must be FDAS_CORR_FFT_F32, FDAS_CORR_GEMM_BF16 or FDAS_CORR_GEMM_F16");
+        return FDAS_E_INVAL;
+    }
     if (!is_pow2(o.median_window) || o.median_window < 32 || o.median_window > 8192) {
         set_error("opts.median_window must be a power of two in [32, 8192]");
         return FDAS_E_INVAL;
@@ -86,12 +90,13 @@ int64_t series_bytes(const Geometry &g, int32_t S, int32_t nz) {
     return 3 * M * 8 + g.nblk * 8 + g.nseg * int64_t(S) * 8 + int64_t(nz) * g.nb * 5;
 }
 
-// Device bytes of the candidate buffers and the harmonic-sum lists of a plan
+// Device bytes of the per-series buffers that depend on the plan's options
+// (candidate buffers, harmonic-sum lists, the matrix correlator's spectrum)
 // for a series of nb bins.
 int64_t candidate_bytes(const fdas_plan_s *p, int64_t nb) {
     const uint32_t cap = p->cand_cap;
     return int64_t(cap) * int64_t(sizeof(DevCand) + sizeof(fdas_cand)) + int64_t(cand_sort_scratch_bytes(cap)) +
-           int64_t(harmsum_scratch_bytes(p->nz, nb, p->hit_cap, p->group_cap)) + 64;
+           int64_t(harmsum_scratch_bytes(p->nz, nb, p->hit_cap, p->group_cap)) + 64 + (p->corr ? nb * 4 : 0);
 }
 
 // Run the whole per-series path on `st`, writing the plane into `plane` and
@@ -124,12 +129,21 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
         X = static_cast<const float2 *>(in_dev);
     }
     if ((e = mark(2)) != hipSuccess) return hip_fail(p, e, "timing event");
-    e = launch_segfft(X, med, p->W, g.nb, p->log2s, p->h, g.nseg, ws.seg, st);
-    if (e != hipSuccess) return hip_fail(p, e, "segment DFT");
-    if ((e = mark(3)) != hipSuccess) return hip_fail(p, e, "timing event");
-    e = launch_correlate(ws.seg, p->d_bank, p->nz, p->tpb, g.nb, p->log2s, p->h, g.nseg, plane, ws.codes,
-                         p->code_inv, st);
-    if (e != hipSuccess) return hip_fail(p, e, "correlate");
+    if (p->corr == FDAS_CORR_FFT_F32) {
+        e = launch_segfft(X, med, p->W, g.nb, p->log2s, p->h, g.nseg, ws.seg, st);
+        if (e != hipSuccess) return hip_fail(p, e, "segment DFT");
+        if ((e = mark(3)) != hipSuccess) return hip_fail(p, e, "timing event");
+        e = launch_correlate(ws.seg, p->d_bank, p->nz, p->tpb, g.nb, p->log2s, p->h, g.nseg, plane, ws.codes,
+                             p->code_inv, st);
+        if (e != hipSuccess) return hip_fail(p, e, "correlate");
+    } else {
+        const bool bf16 = p->corr == FDAS_CORR_GEMM_BF16;
+        e = launch_lowp_spectrum(X, med, p->W, g.nb, bf16, ws.xl, st);
+        if (e != hipSuccess) return hip_fail(p, e, "16-bit spectrum");
+        if ((e = mark(3)) != hipSuccess) return hip_fail(p, e, "timing event");
+        e = launch_corr_gemm(ws.xl, g.nb, p->h, p->d_gemm, p->nz, bf16, p->num_cu, plane, ws.codes, p->code_inv, st);
+        if (e != hipSuccess) return hip_fail(p, e, "matrix correlate");
+    }
     if ((e = mark(4)) != hipSuccess) return hip_fail(p, e, "timing event");
     e = launch_zero_u32(dcount, 6, st);
     if (e != hipSuccess) return hip_fail(p, e, "zero counter");
@@ -187,6 +201,7 @@ static void free_workspace(Workspace &ws) {
     if (ws.seg) (void)hipFree(ws.seg);
     if (ws.plane) (void)hipFree(ws.plane);
     if (ws.codes) (void)hipFree(ws.codes);
+    if (ws.xl) (void)hipFree(ws.xl);
     if (ws.cands) (void)hipFree(ws.cands);
     if (ws.count) (void)hipFree(ws.count);
     if (ws.sort) (void)hipFree(ws.sort);
@@ -215,6 +230,7 @@ fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp) {
     FDAS_ALLOC(ws.seg, g.nseg * int64_t(p->S) * 8);
     FDAS_ALLOC(ws.plane, int64_t(p->nz) * g.nb * 4);
     FDAS_ALLOC(ws.codes, int64_t(p->nz) * g.nb);
+    if (p->corr != FDAS_CORR_FFT_F32) FDAS_ALLOC(ws.xl, g.nb * 4);
     FDAS_ALLOC(ws.cands, int64_t(p->cand_cap) * int64_t(sizeof(DevCand)));
     FDAS_ALLOC(ws.count, 64);
     FDAS_ALLOC(ws.sort, cand_sort_scratch_bytes(p->cand_cap));
@@ -280,6 +296,12 @@ fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, 
     p->W = o.median_window;
     p->nsamp = nsamp;
     p->tpb = o.templates_per_block > 0 ? o.templates_per_block : default_tpb(bank->nz);
+    p->corr = o.correlator;
+    if (p->corr != FDAS_CORR_FFT_F32 && gemm_ksteps(bank->h) > GM_MAX_KSTEPS) {
+        delete p;
+        set_error("the matrix correlators need h <= 271 (zmax <= 510)");
+        return FDAS_E_INVAL;
+    }
     p->cand_cap = uint32_t(o.cand_capacity > 0
                                ? o.cand_capacity
                                : std::min<int64_t>(int64_t(1) << 22,
@@ -308,6 +330,27 @@ fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, 
         delete p;
         set_error(std::string("no HIP device: ") + hipGetErrorString(e));
         return FDAS_E_DEVICE;
+    }
+    {
+        int ncu = 0;
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && ncu > 0)
+            p->num_cu = ncu;
+    }
+    if (p->corr != FDAS_CORR_FFT_F32) {
+        // Template matrix of the matrix correlator (16-bit, fragment order).
+        std::vector<uint8_t> gm(gemm_bank_bytes(p->nz, p->h));
+        build_gemm_bank(reinterpret_cast<const double *>(bank->taps.data()), p->nz, p->h,
+                        p->corr == FDAS_CORR_GEMM_BF16, gm.data());
+        e = hipMalloc(&p->d_gemm, gm.size());
+        if (e == hipSuccess) e = hipMemcpy(p->d_gemm, gm.data(), gm.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (p->d_gemm) (void)hipFree(p->d_gemm);
+            delete p;
+            set_error(std::string("template matrix: ") + hipGetErrorString(e));
+            return FDAS_E_NOMEM;
+        }
+        *out = p;
+        return FDAS_OK;
     }
     // Template bank in the segment domain: taps wrapped circularly (q >= 0 at
     // n = q, q < 0 at n = S + q), FP64 DFT, times 1/S, rounded to float32.
@@ -450,7 +493,8 @@ int64_t fdas_plan_nbins(const fdas_plan_t *plan) { return plan ? plan->nsamp / 2
 
 int64_t fdas_plan_device_bytes(const fdas_plan_t *plan) {
     if (!plan) return 0;
-    int64_t b = int64_t(plan->nz) * plan->S * 8;
+    int64_t b = plan->corr == FDAS_CORR_FFT_F32 ? int64_t(plan->nz) * plan->S * 8
+                                                : int64_t(gemm_bank_bytes(plan->nz, plan->h));
     for (const Workspace &ws : plan->ws)
         if (ws.nsamp)
             b += series_bytes(make_geometry(ws.nsamp, plan->S, plan->h, plan->W), plan->S, plan->nz) +
@@ -476,6 +520,7 @@ void fdas_plan_destroy(fdas_plan_t *plan) {
     for (auto &m : plan->graphs)
         for (auto &kv : m) (void)hipGraphExecDestroy(kv.second);
     if (plan->d_bank) (void)hipFree(plan->d_bank);
+    if (plan->d_gemm) (void)hipFree(plan->d_gemm);
     delete plan;
 }
 

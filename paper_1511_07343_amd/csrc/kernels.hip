@@ -4,6 +4,7 @@
 // complex multiply-scale by every template (step 5), inverse DFT (step 6) and
 // power with edge removal (step 7) fused into one kernel; then harmonic sums,
 // thresholds and local maxima on the resulting f-fdot plane.
+#include "device_common.hpp"
 #include "fft_wg.hpp"
 #include "kernels.hpp"
 
@@ -12,8 +13,6 @@
 namespace fdas {
 
 namespace {
-
-constexpr double kLn2 = 0.69314718055994530942;
 
 // Threads per workgroup for a transform of 2^log2s points.
 constexpr int fft_threads(int log2s) {
@@ -189,21 +188,6 @@ __global__ __launch_bounds__(kMedThreads) void k_median(const float2 *__restrict
     if (t == 0) med[blockIdx.x] = median_sorted(s, w);
 }
 
-// m(k): block medians joined linearly between block centres, flat outside.
-__device__ __forceinline__ double median_curve(const double *__restrict__ med, int64_t nblk, int W,
-                                               int64_t nb, int64_t g) {
-    const double c0 = 0.5 * double(min(int64_t(W), nb) - 1);
-    const int64_t wl = nb - (nblk - 1) * int64_t(W);
-    const double cl = double((nblk - 1) * int64_t(W)) + 0.5 * double(wl - 1);
-    const double x = double(g);
-    if (x <= c0 || nblk == 1) return med[0];
-    if (x >= cl) return med[nblk - 1];
-    const int64_t b = int64_t(floor((x - c0) / double(W)));
-    const double cb = c0 + double(b) * double(W);
-    const double cb1 = (b + 1 == nblk - 1) ? cl : cb + double(W);
-    return med[b] + (med[b + 1] - med[b]) * ((x - cb) / (cb1 - cb));
-}
-
 // -------------------------------------------------------- segment DFTs
 template <int LOG2S>
 __global__ __launch_bounds__(fft_threads(LOG2S)) void k_segfft(const float2 *__restrict__ X,
@@ -253,13 +237,6 @@ __global__ __launch_bounds__(256) void k_normalise(const float2 *__restrict__ X,
 }
 
 // ----------------------------------------------- fused correlation kernel
-// Screening code of a power: min(255, ceil(P / delta)) with code_inv = 1 / delta,
-// never below P / delta (up to one rounding of the product), so integer sums of
-// codes bound power sums from above; NaN and huge powers saturate at 255.
-__device__ __forceinline__ uint8_t power_code(float pw, float code_inv) {
-    return uint8_t(fminf(ceilf(pw * code_inv), 255.f));
-}
-
 // Work item u = (template block tb, segment s), tb-major.  Workgroup i runs
 // item u = (i mod 8) * per + i div 8, so each XCD walks a contiguous range of
 // template blocks over all segments and keeps its templates in its own L2.

@@ -53,6 +53,24 @@ hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, i
                             int log2s, int h, int64_t nseg, float *plane, uint8_t *codes, float code_inv,
                             hipStream_t st);
 
+// Matrix-core correlator (BF16 or FP16 operands, FP32 accumulation).
+// gemm_ksteps(h): K steps of 32 (real K = 2 (2h + 1), zero padded); at most
+// GM_MAX_KSTEPS (the template slice must fit the workgroup's LDS).
+constexpr int GM_MAX_KSTEPS = 34;
+int gemm_ksteps(int h);
+// Template matrix in MFMA fragment order: gemm_bank_bytes(nz, h) bytes,
+// built on the host from the FP64 taps (nz x (2h + 1) complex, tap q at
+// column q + h).
+size_t gemm_bank_bytes(int nz, int h);
+void build_gemm_bank(const double *taps, int nz, int h, bool bf16, void *out);
+// Xhat = X sqrt(ln2 / m(k)) (or X when med is NULL) as 16-bit (Re, Im) pairs.
+hipError_t launch_lowp_spectrum(const float2 *X, const double *med, int W, int64_t nb, bool bf16, uint32_t *out,
+                                hipStream_t st);
+// plane[iz][k] = |sum_q Xhat[k - q] T_iz[q]|^2 and its screening codes (as
+// launch_correlate), over `workgroups` persistent workgroups.  nb % 4 == 0.
+hipError_t launch_corr_gemm(const uint32_t *xl, int64_t nb, int h, const void *bank, int nz, bool bf16,
+                            int workgroups, float *plane, uint8_t *codes, float code_inv, hipStream_t st);
+
 // Harmonic sums over 1..nharm_max harmonics, thresholds and 3x3 local
 // maxima.  thr[i] is the threshold of 2^i harmonics, code_thr[i] (<= 0x8000)
 // the screen's threshold in code units: it must not exceed the code sum of any

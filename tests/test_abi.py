@@ -82,3 +82,26 @@ def test_bad_plan_arguments_rejected_before_device():
     assert lib.fdas_dft_c64(5, 0, 1, None, None, None) == -1
     assert lib.fdas_strerror(-4) == b"candidate capacity exceeded"
     bank.close()
+
+
+def test_matrix_correlator_option_validation():
+    """Plan options are checked before any device work: an unknown correlator,
+    or a matrix correlator with a bank wider than h = 271, is INVAL."""
+    import paper_1511_07343_amd as fdas
+
+    narrow = fdas.make_templates(20.0, 2.0)
+    wide = fdas.make_templates(600.0, 2.0)
+    try:
+        lib = fdas.load()
+        o = fdas._opts(correlator="bf16")
+        o.correlator = 7
+        h = ctypes.c_void_p()
+        assert lib.fdas_plan(narrow._h, 1 << 14, 256, ctypes.byref(o), ctypes.byref(h)) == -1
+        o = fdas._opts(correlator="f16")
+        assert lib.fdas_plan(wide._h, 1 << 14, 4096, ctypes.byref(o), ctypes.byref(h)) == -1
+        assert b"h <= 271" in lib.fdas_last_error()
+        with pytest.raises(ValueError):
+            fdas._opts(correlator="tf32")
+    finally:
+        narrow.close()
+        wide.close()
