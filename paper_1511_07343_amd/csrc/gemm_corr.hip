@@ -58,11 +58,14 @@ __host__ __device__ inline uint16_t to_half_bits(float x) {
 constexpr int GM_WAVES = 4;
 constexpr int GM_RT = 8;                         // row tiles of 16 bins per wave
 constexpr int GM_ROWS = GM_WAVES * GM_RT * 16;   // bins per row block
-constexpr int GM_TZ = 32;                        // templates per slice (64 output columns)
+constexpr int GM_TZ = 32;                        // templates per slice
+constexpr int GM_CT = 2 * GM_TZ / 16;            // column tiles: Re, then Im, of the slice's templates
 constexpr int GM_WIN = 16;                       // A fragments kept per wave (power of two >= GM_RT + 1)
 constexpr int GM_FRAG = 64;                      // 16-byte fragments per MFMA operand (one per lane)
-constexpr int GM_SLICE_FRAGS = 4 * GM_FRAG;      // B fragments of one K step of a slice
+constexpr int GM_SLICE_FRAGS = GM_CT * GM_FRAG;  // B fragments of one K step of a slice
 constexpr int GM_WORDS(int nk) { return GM_ROWS + 16 * nk; }  // window words per copy
+// window words loaded per thread (copies are written from registers)
+constexpr int GM_WLOAD = (GM_WORDS(GM_MAX_KSTEPS) + 3 + 64 * GM_WAVES - 1) / (64 * GM_WAVES);
 
 // Templates scaled by 16 (exactly) so that FP16 keeps the tails of the taps
 // away from its subnormal range; powers are scaled back by 1/256.
@@ -86,8 +89,8 @@ __global__ __launch_bounds__(256) void k_lowp_spectrum(const float2 *__restrict_
 
 // One workgroup: the B fragments of one template slice (all K) staged in LDS,
 // then row blocks of GM_ROWS bins, each through a spectrum window in LDS.
-// Wave w owns rows [128 w, 128 w + 128) of a block (8 row tiles) and all 4
-// column tiles (Re of templates 0-15 and 16-31, then Im of the same).
+// Wave w owns rows [128 w, 128 w + 128) of a block (8 row tiles) and all
+// GM_CT column tiles (Re of the slice's templates, 16 per tile, then Im).
 //
 // The A fragment of (row tile rt, K step ks) holds window words
 // u = (GM_ROWS - 1 - row) + 16 ks + 4 (l / 16) .. + 3, which depend on ks - rt
@@ -95,6 +98,10 @@ __global__ __launch_bounds__(256) void k_lowp_spectrum(const float2 *__restrict_
 // registers and loads one new fragment per K step.  The window is stored in
 // four copies shifted by one word, so that every lane's fragment is a 16-byte
 // aligned LDS read (copy (3 - l % 16) mod 4).
+//
+// The next block's window is loaded into registers before this block's
+// powers are stored, so that the stores drain while the next block runs
+// (vector-memory counters count loads and stores together).
 template <bool BF16>
 __global__ __launch_bounds__(64 * GM_WAVES, 1) void k_corr_gemm(
     const uint32_t *__restrict__ xl, int64_t nb, int h, int nk, const uint4 *__restrict__ bfrag, int nz, int nsl,
@@ -114,6 +121,21 @@ __global__ __launch_bounds__(64 * GM_WAVES, 1) void k_corr_gemm(
     const int64_t total = int64_t(nsl) * nrb;
     const int64_t item0 = int64_t(blockIdx.x) * per;
     const int64_t item1 = min(total, item0 + per);
+    if (item0 >= item1) return;
+    // window words W[u] = xl[P0 - u], u < uw + 3 (zero outside the spectrum),
+    // thread t holding u = t + 256 i
+    uint32_t wreg[GM_WLOAD];
+    auto load_window = [&](int64_t item) {
+        const int sl = int(item / nrb);
+        const int64_t p0 = (item - int64_t(sl) * nrb) * GM_ROWS + GM_ROWS - 1 + h;
+#pragma unroll
+        for (int i = 0; i < GM_WLOAD; ++i) {
+            const int u = t + 64 * GM_WAVES * i;
+            const int64_t p = p0 - u;
+            wreg[i] = (u < uw + 3 && p >= 0 && p < nb) ? xl[p] : 0u;
+        }
+    };
+    load_window(item0);
     int cur_slice = -1;
     for (int64_t item = item0; item < item1; ++item) {
         const int sl = int(item / nrb);
@@ -124,58 +146,62 @@ __global__ __launch_bounds__(64 * GM_WAVES, 1) void k_corr_gemm(
             for (int i = t; i < nk * GM_SLICE_FRAGS; i += 64 * GM_WAVES) bl[i] = src[i];
             cur_slice = sl;
         }
-        // window word u = xl[P0 - u] (zero outside the spectrum); copy s holds u + s
-        const int64_t p0 = k0 + GM_ROWS - 1 + h;
-        for (int i = t; i < 4 * uw; i += 64 * GM_WAVES) {
-            const int s = i / uw;
-            const int64_t p = p0 - (i - s * uw) - s;
-            win[i] = (p >= 0 && p < nb) ? xl[p] : 0u;
+        // copy s holds W[v + s] at v
+#pragma unroll
+        for (int i = 0; i < GM_WLOAD; ++i) {
+            const int u = t + 64 * GM_WAVES * i;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int v = u - c;
+                if (v >= 0 && v < uw) win[c * uw + v] = wreg[i];
+            }
         }
         __syncthreads();
 
-        f32x4 acc[GM_RT][4];
+        f32x4 acc[GM_RT][GM_CT];
 #pragma unroll
         for (int rt = 0; rt < GM_RT; ++rt)
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int ct = 0; ct < GM_CT; ++ct) acc[rt][ct] = f32x4{0.f, 0.f, 0.f, 0.f};
         uint4 F[GM_WIN];
 #pragma unroll
         for (int d = 1; d < GM_RT; ++d)  // F(-7) .. F(-1)
             F[(GM_WIN - d) % GM_WIN] = *reinterpret_cast<const uint4 *>(win + fbase - 16 * d);
         F[0] = *reinterpret_cast<const uint4 *>(win + fbase);
-        uint4 b[4];
+        uint4 b[GM_CT];
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) b[ct] = bl[ct * GM_FRAG + lane];
+        for (int ct = 0; ct < GM_CT; ++ct) b[ct] = bl[ct * GM_FRAG + lane];
         for (int kb = 0; kb < nk; kb += GM_WIN) {
 #pragma unroll
             for (int j = 0; j < GM_WIN; ++j) {
                 const int ks = kb + j;
                 if (ks < nk) {
                     // prefetch step ks + 1 (F(ks + 1) replaces F(ks - 15), no longer used)
-                    uint4 bn[4];
+                    uint4 bn[GM_CT];
                     if (ks + 1 < nk) {
                         F[(j + 1) % GM_WIN] = *reinterpret_cast<const uint4 *>(win + fbase + 16 * (ks + 1));
 #pragma unroll
-                        for (int ct = 0; ct < 4; ++ct) bn[ct] = bl[((ks + 1) * 4 + ct) * GM_FRAG + lane];
+                        for (int ct = 0; ct < GM_CT; ++ct) bn[ct] = bl[((ks + 1) * GM_CT + ct) * GM_FRAG + lane];
                     }
 #pragma unroll
                     for (int rt = 0; rt < GM_RT; ++rt) {
                         const uint4 a = F[(j - rt + GM_WIN) % GM_WIN];
 #pragma unroll
-                        for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = Mfma<BF16>::op(a, b[ct], acc[rt][ct]);
+                        for (int ct = 0; ct < GM_CT; ++ct) acc[rt][ct] = Mfma<BF16>::op(a, b[ct], acc[rt][ct]);
                     }
                     if (ks + 1 < nk) {
 #pragma unroll
-                        for (int ct = 0; ct < 4; ++ct) b[ct] = bn[ct];
+                        for (int ct = 0; ct < GM_CT; ++ct) b[ct] = bn[ct];
                     }
                 }
             }
         }
+        if (item + 1 < item1) load_window(item + 1);
 
-        // powers: column tiles 0 / 1 are Re of templates i16 / 16 + i16, tiles
-        // 2 / 3 their Im; rows 4 (l / 16) + r of each row tile
+        // powers: column tile c < GM_CT / 2 is Re of templates 16 c + i16, tile
+        // c + GM_CT / 2 their Im; rows 4 (l / 16) + r of each row tile
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
+        for (int half = 0; half < GM_CT / 2; ++half) {
             const int z = sl * GM_TZ + 16 * half + i16;
             if (z >= nz) continue;
             float *__restrict__ prow = plane + int64_t(z) * nb;
@@ -184,7 +210,7 @@ __global__ __launch_bounds__(64 * GM_WAVES, 1) void k_corr_gemm(
             for (int rt = 0; rt < GM_RT; ++rt) {
                 const int64_t k = k0 + 128 * wave + 16 * rt + 4 * kg;
                 if (k >= nb) continue;
-                const f32x4 re = acc[rt][half], im = acc[rt][half + 2];
+                const f32x4 re = acc[rt][half], im = acc[rt][half + GM_CT / 2];
                 float4 pw;
                 pw.x = fmaf(re[0], re[0], im[0] * im[0]) * power_scale;
                 pw.y = fmaf(re[1], re[1], im[1] * im[1]) * power_scale;
@@ -213,7 +239,7 @@ void build_gemm_bank(const double *taps, int nz, int h, bool bf16, void *out) {
     size_t idx = 0;
     for (int sl = 0; sl < nsl; ++sl)
         for (int ks = 0; ks < nk; ++ks)
-            for (int ct = 0; ct < 4; ++ct)
+            for (int ct = 0; ct < GM_CT; ++ct)
                 for (int l = 0; l < 64; ++l)
                     for (int s = 0; s < 8; ++s, ++idx) {
                         const int c = 32 * ks + 8 * (l / 16) + s;  // K index
