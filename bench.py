@@ -9,11 +9,23 @@ whole path (real DFT, normalisation, segment DFTs, template multiply, inverse
 DFTs, powers, harmonic sums, peaks, candidates to the host) with the series
 already resident in device memory.
 
-Prints one JSON line: the plain per-trial rate as ``value``, plus the batched
-rate, a short served burst (host series in, PCIe included) with p50/p99
-latency, the roofline of the dominant kernel (the fused multiply / inverse
-DFT / power kernel, timed with HIP events on its own stream during the timed
-steps) and the FP64 CPU oracle timed on a bounded sample of the same trial.
+Prints one JSON line: the plain per-trial rate as ``value``, then
+  batched    64 distinct trials of 2^23 samples (0-3 pulsars each) through
+             fdas_search_batch (graph-captured launches, autotuned segment
+             length and templates per block), series resident in HBM;
+  served     the 6000-request trace (20/30/50 % of 2^21/2^22/2^23 samples,
+             Poisson arrivals filling 530 s, 5 % with a pulsar) replayed
+             through the continuous-batching server from host memory (PCIe
+             included): saturated (a bounded number in flight) for
+             throughput, and the first requests at their arrival times,
+             compressed 10x, for p50/p99 latency;
+  precision  16 trials of 2^22 samples, 801 templates (z in [-400, 400],
+             step 1): FP32 FFT correlation against the BF16 and FP16
+             matrix-core correlators, with power error and candidate
+             agreement against the FP64 oracle on a band of bins;
+the roofline of the dominant kernel (the fused multiply / inverse DFT / power
+kernel, timed with HIP events on its own stream during the timed steps) and
+the FP64 CPU oracle timed on a bounded sample of the same trial.
 """
 from __future__ import annotations
 
@@ -80,6 +92,191 @@ def read_traffic():
         return None
 
 
+def _gen(spec):
+    """Worker: one synthetic series (kind, args) -> float32 array."""
+    import synth
+    kind, a = spec
+    if kind == "batch":
+        return synth._trial_with_random_pulsars(1 << 23, 1000 + a, None).x
+    if kind == "ring":
+        n, seed, pulsar = a
+        return synth._trial_with_random_pulsars(n, seed, 1 if pulsar else 0).x
+    raise ValueError(kind)
+
+
+def generate(specs, workers: int = 16):
+    """Series for `specs`, generated in a process pool (before any GPU use)."""
+    import multiprocessing as mp
+    workers = max(1, min(workers, len(os.sched_getaffinity(0)), len(specs)))
+    if workers == 1:
+        return [_gen(sp) for sp in specs]
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.map(_gen, specs)
+
+
+RING = 8            # distinct host series per length class in the served replay
+C4_LENGTHS = (1 << 21, 1 << 22, 1 << 23)
+
+
+def bench_batched(fdas, bank, xs, per_call: int):
+    """64 distinct trials through fdas_search_batch in calls of per_call."""
+    import torch
+    seg_b, tpb_b, tune_ms = fdas.autotune(bank, N, nharm_max=NHARM, sigma=SIGMA)
+    log(f"batched: {len(xs)} trials, {per_call} per call, segment {seg_b}, {tpb_b} templates per block")
+    planb = fdas.Plan(bank, N, seg_b, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb_b)
+    bcap = 1 << 20
+    bout = fdas.pinned_candidates(bcap * per_call)
+    planb.search_batch(xs[:per_call], caps=[bcap] * per_call, out=bout)  # captures the graphs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(0, len(xs), per_call):
+        chunk = xs[i:i + per_call]
+        planb.search_batch(chunk, caps=[bcap] * len(chunk), out=bout)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    planb.close()
+    return {"value": round(len(xs) / tb, 3), "unit": "DM trials/s", "trials": len(xs),
+            "trials_per_call": per_call, "ms_per_trial": round(1e3 * tb / len(xs), 4),
+            "data": "64 distinct trials, seeds 1000-1063, 0-3 pulsars each, resident in HBM",
+            "autotuned": {"segment": seg_b, "templates_per_block": tpb_b,
+                          "segment_dft_plus_correlate_ms": round(tune_ms, 4)}}
+
+
+def _replay(fdas, srv, trace, ring, paced_speedup, inflight):
+    """Submit the trace's requests (from the ring of host series) and collect
+    results.  paced_speedup > 0: request i is submitted at t_arrival / speedup;
+    else as soon as fewer than `inflight` are outstanding.  Returns
+    (wall seconds, latencies in s, candidates found)."""
+    import numpy as np
+    lat, found = [], 0
+    t0 = time.perf_counter()
+    nxt = 0
+    done = 0
+    slot = {n: 0 for n in C4_LENGTHS}
+    while done < len(trace):
+        while nxt < len(trace):
+            e = trace[nxt]
+            if paced_speedup > 0:
+                if time.perf_counter() - t0 < e["t_arrival"] / paced_speedup:
+                    break
+            elif nxt - done >= inflight:
+                break
+            n = e["nsamp"]
+            if e["has_pulsar"]:
+                x = ring[n][0]
+            else:
+                x = ring[n][1 + slot[n] % (RING - 1)]
+                slot[n] += 1
+            srv.submit(x, tag=nxt)
+            nxt += 1
+        r = srv.poll(timeout_ms=1)
+        if r is None:
+            continue
+        lat.append(r[3])
+        found += r[2]
+        done += 1
+    return time.perf_counter() - t0, np.asarray(lat), found
+
+
+def bench_served(fdas, bank, ring, requests: int, paced: int, speedup: float):
+    """The served trace: saturated replay (throughput) and a paced replay of
+    its first `paced` requests at `speedup` x real time (latency)."""
+    import numpy as np
+    import synth
+    trace = synth.served_trace()[:requests]
+    srv = fdas.Server(bank, SEG, N, max_slots=4, nharm_max=NHARM, sigma=SIGMA)
+    srv.submit(ring[N][1], tag=1 << 40)  # warm the buffers of the longest length
+    srv.poll(timeout_ms=120000)
+    log(f"served: saturated replay of {len(trace)} requests")
+    ts, lat_s, found = _replay(fdas, srv, trace, ring, 0.0, inflight=8)
+    out = {"value": round(len(trace) / ts, 3), "unit": "DM trials/s", "requests": len(trace),
+           "mix": "20/30/50 % of 2^21/2^22/2^23 samples, 5 % with a pulsar",
+           "arrival": "saturated: next request submitted while 8 are in flight; host series, PCIe included",
+           "data": f"ring of {RING} seeded host series per length (one with a pulsar), recycled",
+           "candidates": int(found),
+           "latency_ms": {"p50": round(1e3 * float(np.percentile(lat_s, 50)), 2),
+                          "p99": round(1e3 * float(np.percentile(lat_s, 99)), 2)},
+           "realtime_need": {"value": round(6000 / 530.0, 3), "unit": "DM trials/s"}}
+    if paced > 0:
+        sub = trace[:paced]
+        log(f"served: {len(sub)} requests paced at {speedup:g}x real time")
+        tp, lat_p, _ = _replay(fdas, srv, sub, ring, speedup, inflight=1 << 30)
+        out["paced"] = {"requests": len(sub), "speedup": speedup,
+                        "offered_rate": round(speedup * 6000 / 530.0, 3), "unit": "DM trials/s",
+                        "wall_s": round(tp, 3),
+                        "latency_ms": {"p50": round(1e3 * float(np.percentile(lat_p, 50)), 2),
+                                       "p99": round(1e3 * float(np.percentile(lat_p, 99)), 2)}}
+    srv.close()
+    return out
+
+
+C5_ZMAX, C5_DZ, C5_N = 400.0, 1.0, 1 << 22
+
+
+def bench_precision(fdas, ntrials: int, band: int):
+    """C5: the three correlators on 16 trials of 2^22 samples (801 templates);
+    power error and candidate agreement against the FP64 oracle on a band of
+    `band` bins around the strongest pulsar of the first trial that has one
+    (one harmonic, 6 sigma)."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    import synth
+    trials = synth.precision_trials(ntrials)
+    xs = [torch.from_numpy(t.x).cuda() for t in trials]
+    jref = next((j for j, t in enumerate(trials) if t.pulsars), 0)
+    ref = trials[jref]
+    nb = C5_N // 2
+    taps, zs, h = O.template_taps(C5_ZMAX, C5_DZ)
+    centre = int(round(max(ref.pulsars, key=lambda p: p.amp).r)) if ref.pulsars else nb // 3
+    k0 = int(min(max(centre - band // 2, h), nb - band - h))
+    Xh = O.normalise(O.real_spectrum(ref.x), 1024)
+    t0 = time.perf_counter()
+    P_orc = O.correlate(Xh[k0 - h:k0 + band + h], taps)[:, h:h + band]
+    t_orc = time.perf_counter() - t0
+    thr = O.thresholds(SIGMA, [1])[1]
+    pk = O.find_peaks(P_orc, thr)
+    inner = (pk[:, 1] >= 1) & (pk[:, 1] < band - 1)
+    o_set = {(int(iz), int(k) + k0) for iz, k in pk[inner]}
+    bank = fdas.make_templates(C5_ZMAX, C5_DZ)
+    plane = torch.empty((bank.nz, nb), dtype=torch.float32, device="cuda")
+    big = P_orc >= 1.0
+    out = {"trials": ntrials, "nsamp": C5_N, "templates": bank.nz, "nharm": 1,
+           "oracle_band": {"k0": k0, "bins": band, "trial_seed": ref.seed, "oracle_s": round(t_orc, 2),
+                           "oracle_candidates": len(o_set)}}
+    for corr in ("fft", "bf16", "f16"):
+        plan = fdas.Plan(bank, C5_N, SEG, nharm_max=1, sigma=SIGMA, correlator=corr)
+        plan.search(xs[0])
+        torch.cuda.synchronize()
+        plan.enable_timing(True)
+        t0 = time.perf_counter()
+        for x in xs:
+            plan.search(x)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st, nt = plan.stage_times()
+        plan.enable_timing(False)
+        cands, n = plan.search(xs[jref], plane=plane)
+        torch.cuda.synchronize()
+        P = plane[:, k0:k0 + band].cpu().numpy().astype(np.float64)
+        err = np.abs(P - P_orc)
+        rel = err[big] / P_orc[big]
+        sel = (cands["nharm"] == 1) & (cands["k"] >= k0 + 1) & (cands["k"] < k0 + band - 1)
+        g_set = {(int(c["iz"]), int(c["k"])) for c in cands[sel]}
+        both = len(g_set & o_set)
+        out[corr] = {"value": round(ntrials / dt, 3), "unit": "DM trials/s",
+                     "correlate_ms": round(st["correlate"] / nt, 4),
+                     "power_rel_err": {"max": float(rel.max()), "rms": float(np.sqrt(np.mean(rel ** 2))),
+                                       "over": "cells with P >= 1 in the band"},
+                     "candidates": {"gpu": len(g_set), "oracle": len(o_set), "common": both,
+                                    "agreement": round(both / max(1, len(o_set | g_set)), 4)}}
+        plan.close()
+    del plane
+    bank.close()
+    return out
+
+
 def cpu_baseline(trial, bins: int):
     """Time the FP64 oracle on a bounded sample of one trial: the real DFT and
     normalisation of the whole series, then the direct correlation, harmonic
@@ -126,8 +323,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=8, help="trials per batched launch")
-    ap.add_argument("--served", type=int, default=24, help="requests in the served burst (0 = skip)")
+    ap.add_argument("--batch", type=int, default=16, help="trials per fdas_search_batch call")
+    ap.add_argument("--batch-trials", type=int, default=64, help="distinct trials in the batched run (0 = skip)")
+    ap.add_argument("--served", type=int, default=6000, help="requests of the served trace replayed (0 = skip)")
+    ap.add_argument("--paced", type=int, default=1000, help="requests replayed at their arrival times")
+    ap.add_argument("--speedup", type=float, default=10.0, help="time compression of the paced replay")
+    ap.add_argument("--precision-trials", type=int, default=16, help="trials of the precision comparison (0 = skip)")
+    ap.add_argument("--precision-band", type=int, default=65536, help="oracle band of the precision comparison")
     ap.add_argument("--cpu-bins", type=int, default=1 << 17, help="oracle sample width in bins (0 = skip)")
     ap.add_argument("--plain-only", action="store_true", help="only the plain per-trial loop (profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -139,6 +341,22 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    # host inputs of the batched and served runs, generated in a process pool
+    # before anything touches the GPU
+    extra = not args.plain_only
+    specs = []
+    if extra and args.batch_trials > 0:
+        specs += [("batch", i) for i in range(args.batch_trials)]
+    if extra and args.served > 0:
+        specs += [("ring", (n, 60000 + 100 * c + i, i == 0)) for c, n in enumerate(C4_LENGTHS) for i in range(RING)]
+    if specs:
+        log(f"generating {len(specs)} host series")
+    gen = generate(specs)
+    batch_host = gen[:args.batch_trials] if extra and args.batch_trials > 0 else []
+    ring_host = gen[len(batch_host):]
+    ring = {n: ring_host[c * RING:(c + 1) * RING] for c, n in enumerate(C4_LENGTHS)} if ring_host else {}
+
     import torch
 
     import paper_1511_07343_amd as fdas
@@ -202,51 +420,19 @@ def main():
                      "hbm_GBs": round(correlate_bytes(nseg, nz, SEG, nb) / (corr_ms * 1e-3) / 1e9, 1)},
     }
 
-    if not args.plain_only and args.batch > 0:
-        log("autotune (segment length, templates per block) for the batched path")
-        seg_b, tpb_b, tune_ms = fdas.autotune(bank, N, nharm_max=NHARM, sigma=SIGMA)
-        log(f"batched: {args.batch} trials per call, segment {seg_b}, {tpb_b} templates per block")
-        planb = fdas.Plan(bank, N, seg_b, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb_b)
-        bx = [xs[i % len(xs)] for i in range(args.batch)]
-        bcap = 1 << 20
-        bout = fdas.pinned_candidates(bcap * len(bx))
-        planb.search_batch(bx, caps=[bcap] * len(bx), out=bout)
-        torch.cuda.synchronize()
-        reps = 3
-        tb0 = time.perf_counter()
-        for _ in range(reps):
-            planb.search_batch(bx, caps=[bcap] * len(bx), out=bout)
-        torch.cuda.synchronize()
-        tb = time.perf_counter() - tb0
-        planb.close()
-        out["batched"] = {"value": round(reps * len(bx) / tb, 3), "unit": "DM trials/s",
-                          "trials_per_call": len(bx), "ms_per_trial": round(1e3 * tb / (reps * len(bx)), 4),
-                          "autotuned": {"segment": seg_b, "templates_per_block": tpb_b,
-                                        "segment_dft_plus_correlate_ms": round(tune_ms, 4)}}
+    if batch_host:
+        bxs = [torch.from_numpy(x).to(dev) for x in batch_host]
+        del batch_host
+        out["batched"] = bench_batched(fdas, bank, bxs, args.batch)
+        del bxs
     plan.close()
 
-    if not args.plain_only and args.served > 0:
-        log(f"served burst: {args.served} requests")
-        rng = np.random.default_rng(4)
-        lens = rng.choice([1 << 21, 1 << 22, 1 << 23], size=args.served, p=[0.2, 0.3, 0.5])
-        host = {n: synth.make_series(int(n), seed=40000 + int(n).bit_length()).x for n in set(lens.tolist())}
-        srv = fdas.Server(bank, SEG, N, max_slots=4, nharm_max=NHARM, sigma=SIGMA)
-        srv.submit(host[N], tag=999999)  # warm the buffers of the longest length
-        srv.poll(timeout_ms=120000)
-        ts0 = time.perf_counter()
-        for i, n in enumerate(lens):
-            srv.submit(host[int(n)], tag=i)
-        lats = []
-        for _ in range(args.served):
-            r = srv.poll(timeout_ms=120000)
-            lats.append(r[3])
-        ts = time.perf_counter() - ts0
-        srv.close()
-        out["served"] = {"value": round(args.served / ts, 3), "unit": "DM trials/s",
-                         "requests": args.served, "mix": "20/30/50 % of 2^21/2^22/2^23 samples",
-                         "arrival": "all submitted at once (saturated); host series, PCIe copy included",
-                         "latency_ms": {"p50": round(1e3 * float(np.percentile(lats, 50)), 2),
-                                        "p99": round(1e3 * float(np.percentile(lats, 99)), 2)}}
+    if ring:
+        out["served"] = bench_served(fdas, bank, ring, args.served, args.paced, args.speedup)
+
+    if extra and args.precision_trials > 0:
+        log("precision variant: FFT FP32 vs BF16 / FP16 matrix correlators")
+        out["precision"] = bench_precision(fdas, args.precision_trials, args.precision_band)
 
     if args.calib_copy_mib > 0:
         nbytes = args.calib_copy_mib << 20
