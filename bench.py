@@ -371,7 +371,7 @@ def main():
     bank = fdas.make_templates(ZMAX, DZ)
     plan = fdas.Plan(bank, N, SEG, nharm_max=NHARM, sigma=SIGMA)
     nz, h = bank.nz, bank.h
-    L = SEG - 2 * h
+    L = (SEG - 2 * h) & ~3
     nb = N // 2
     nseg = -(-nb // L)
     torch.cuda.synchronize()

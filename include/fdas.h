@@ -124,7 +124,9 @@ fdas_status fdas_significance(double power, int32_t nharm, double *sigma);
  * FP64 and scaled by 1/seg -- the "scale" of the multiply step), and every
  * device work buffer, allocated once.  seg is the overlap-save segment length
  * (Sec. 2, Sec. 4 steps 3-6): a power of two in [256, 8192], >= 4h; each
- * segment yields seg - 2h valid bins.  Needs a visible GPU (it allocates).
+ * segment yields seg - 2h valid bins, of which the first (seg - 2h) rounded
+ * down to a multiple of 4 are kept (the rest come from the next segment).
+ * Needs a visible GPU (it allocates).
  * Errors: INVAL (nsamp, seg, opts), NOMEM, DEVICE.  A plan is not
  * thread-safe; calls on it are ordered on the stream they are given. */
 fdas_status fdas_plan(const fdas_bank *bank, int64_t nsamp, int32_t seg,
@@ -147,10 +149,11 @@ void fdas_plan_destroy(fdas_plan_t *plan);
  *                   complete when the stream is).
  * Errors: INVAL, DEVICE, OVERFLOW (cap or cand_capacity too small: the first
  * min(cap, found) candidates in sorted order of those captured are returned
- * and *ncands holds the true count; also when the internal list of cells
- * that may reach a threshold (4 x cand_capacity cells in 2 x cand_capacity
- * groups of 16 columns) overflowed, in which case the candidates are
- * incomplete and *ncands is a lower bound). */
+ * and *ncands holds the true count; also when the internal list of bins
+ * that may reach a threshold overflowed (4 x cand_capacity bins in
+ * 2 x cand_capacity groups of 32 columns; with the automatic capacity, at
+ * least every bin of planes up to 2^24 bins), in which case the candidates
+ * are incomplete and *ncands is a lower bound). */
 fdas_status fdas_search(fdas_plan_t *plan, int32_t in_kind, const void *in_dev,
                         float *plane_dev, fdas_cand *cands_host, int64_t cap,
                         int64_t *ncands, void *hip_stream);
@@ -167,7 +170,7 @@ fdas_status fdas_plan_stage_times(const fdas_plan_t *plan, double *ms_out, int64
 
 /* Work counts of the last fdas_search on this plan (diagnostics): out3[0]
  * candidates found, out3[1] plane cells the harmonic-sum screen passed on to
- * the exact FP32 sums, out3[2] groups of 16 columns holding those cells.
+ * the exact FP32 sums, out3[2] groups of 32 columns holding those cells.
  * INVAL if no search has completed on the plan. */
 fdas_status fdas_plan_search_counts(const fdas_plan_t *plan, int64_t *out3);
 

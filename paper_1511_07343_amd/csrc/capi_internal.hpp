@@ -35,7 +35,7 @@ struct Workspace {
     double *med = nullptr;   // block medians of |X|^2
     float2 *seg = nullptr;   // segment spectra, nseg x S
     float *plane = nullptr;  // f-fdot plane, nz x nb
-    uint8_t *codes = nullptr;  // screening codes of the plane, nz x nb
+    uint8_t *codes = nullptr;  // screening codes of the plane's 2-bin blocks, nz x nb/2
     uint32_t *xl = nullptr;    // 16-bit spectrum of the matrix correlator, nb words
     DevCand *cands = nullptr;     // unordered records from the harmonic-sum kernel
     uint32_t *count = nullptr;    // their count (may exceed the capacity)

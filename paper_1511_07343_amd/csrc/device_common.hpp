@@ -31,4 +31,18 @@ __device__ __forceinline__ uint8_t power_code(float pw, float code_inv) {
     return uint8_t(fminf(ceilf(pw * code_inv), 255.f));
 }
 
+// Code of a 2-bin block: the larger of its bins' codes (255 if either is NaN,
+// which fmaxf alone would drop).
+__device__ __forceinline__ uint8_t block_code(float a, float b, float code_inv) {
+    float m = fmaxf(a, b);
+    const float sum = a + b;
+    if (!(sum == sum)) m = INFINITY;
+    return uint8_t(fminf(ceilf(m * code_inv), 255.f));
+}
+
+// The codes of the two 2-bin blocks of 4 consecutive bins, as 2 bytes.
+__device__ __forceinline__ uint16_t block_codes4(float4 p, float code_inv) {
+    return uint16_t(block_code(p.x, p.y, code_inv)) | uint16_t(uint16_t(block_code(p.z, p.w, code_inv)) << 8);
+}
+
 }  // namespace fdas

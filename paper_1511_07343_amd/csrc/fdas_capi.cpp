@@ -77,7 +77,7 @@ Geometry make_geometry(int64_t nsamp, int32_t S, int32_t h, int32_t W) {
     Geometry g;
     g.nsamp = nsamp;
     g.nb = nsamp / 2;
-    g.L = S - 2 * h;
+    g.L = (S - 2 * h) & ~3;  // a multiple of 4: store chunks and code blocks never straddle two segments
     g.nseg = (g.nb + g.L - 1) / g.L;
     g.nblk = (g.nb + W - 1) / W;
     return g;
@@ -87,7 +87,7 @@ Geometry make_geometry(int64_t nsamp, int32_t S, int32_t h, int32_t W) {
 // spectra, plane and its screening codes) for a given geometry.
 int64_t series_bytes(const Geometry &g, int32_t S, int32_t nz) {
     const int64_t M = g.nb;
-    return 3 * M * 8 + g.nblk * 8 + g.nseg * int64_t(S) * 8 + int64_t(nz) * g.nb * 5;
+    return 3 * M * 8 + g.nblk * 8 + g.nseg * int64_t(S) * 8 + int64_t(nz) * g.nb * 4 + int64_t(nz) * (g.nb / 2);
 }
 
 // Device bytes of the per-series buffers that depend on the plan's options
@@ -229,7 +229,7 @@ fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp) {
     FDAS_ALLOC(ws.med, g.nblk * 8);
     FDAS_ALLOC(ws.seg, g.nseg * int64_t(p->S) * 8);
     FDAS_ALLOC(ws.plane, int64_t(p->nz) * g.nb * 4);
-    FDAS_ALLOC(ws.codes, int64_t(p->nz) * g.nb);
+    FDAS_ALLOC(ws.codes, int64_t(p->nz) * (g.nb / 2));
     if (p->corr != FDAS_CORR_FFT_F32) FDAS_ALLOC(ws.xl, g.nb * 4);
     FDAS_ALLOC(ws.cands, int64_t(p->cand_cap) * int64_t(sizeof(DevCand)));
     FDAS_ALLOC(ws.count, 64);
@@ -306,7 +306,12 @@ fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, 
                                ? o.cand_capacity
                                : std::min<int64_t>(int64_t(1) << 22,
                                                    std::max<int64_t>(int64_t(1) << 16, int64_t(bank->nz) * (nsamp / 2) / 256)));
-    p->hit_cap = uint32_t(std::min<int64_t>(int64_t(p->cand_cap) * 4, int64_t(1) << 30));
+    // Bins the harmonic-sum screen may pass on: 4 x the candidate capacity,
+    // and with the automatic capacity at least every bin of planes up to 2^24
+    // bins (dense low-threshold searches flag most blocks).
+    int64_t cells = int64_t(p->cand_cap) * 4;
+    if (o.cand_capacity <= 0) cells = std::max<int64_t>(cells, std::min<int64_t>(int64_t(bank->nz) * (nsamp / 2), int64_t(1) << 24));
+    p->hit_cap = uint32_t(std::min<int64_t>(cells, int64_t(1) << 30));
     p->group_cap = std::max<uint32_t>(p->hit_cap / 2, 1u);
     int levels = 0;
     while ((1 << levels) < o.nharm_max) ++levels;

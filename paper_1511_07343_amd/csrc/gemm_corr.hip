@@ -205,7 +205,7 @@ __global__ __launch_bounds__(64 * GM_WAVES, 1) void k_corr_gemm(
             const int z = sl * GM_TZ + 16 * half + i16;
             if (z >= nz) continue;
             float *__restrict__ prow = plane + int64_t(z) * nb;
-            uint8_t *__restrict__ qrow = codes + int64_t(z) * nb;
+            uint8_t *__restrict__ qrow = codes + int64_t(z) * (nb / 2);
 #pragma unroll
             for (int rt = 0; rt < GM_RT; ++rt) {
                 const int64_t k = k0 + 128 * wave + 16 * rt + 4 * kg;
@@ -217,9 +217,7 @@ __global__ __launch_bounds__(64 * GM_WAVES, 1) void k_corr_gemm(
                 pw.z = fmaf(re[2], re[2], im[2] * im[2]) * power_scale;
                 pw.w = fmaf(re[3], re[3], im[3] * im[3]) * power_scale;
                 *reinterpret_cast<float4 *>(prow + k) = pw;
-                *reinterpret_cast<uint32_t *>(qrow + k) =
-                    uint32_t(power_code(pw.x, code_inv)) | (uint32_t(power_code(pw.y, code_inv)) << 8) |
-                    (uint32_t(power_code(pw.z, code_inv)) << 16) | (uint32_t(power_code(pw.w, code_inv)) << 24);
+                *reinterpret_cast<uint16_t *>(qrow + (k >> 1)) = block_codes4(pw, code_inv);
             }
         }
     }

@@ -25,6 +25,11 @@ constexpr int corr_threads(int log2s) { return fft_threads(log2s); }
 // 8 XCDs on MI355X; workgroups are dispatched to XCDs round-robin by index.
 constexpr int kXcds = 8;
 
+// Valid points per segment: S - 2h rounded down to a multiple of 4, so that
+// the correlation's 4-bin store chunks (and the 2-bin blocks of the screening
+// codes) never straddle two segments.
+__host__ __device__ constexpr int64_t seg_valid(int S, int h) { return int64_t((S - 2 * h) & ~3); }
+
 // ------------------------------------------------------------- plain DFT
 template <int LOG2S, int DIR>
 __global__ __launch_bounds__(fft_threads(LOG2S)) void k_dft(const float2 *__restrict__ in,
@@ -198,7 +203,7 @@ __global__ __launch_bounds__(fft_threads(LOG2S)) void k_segfft(const float2 *__r
     __shared__ float2 lds[Sh::LDS_FLOAT2];
     const int t = threadIdx.x;
     const int64_t s = blockIdx.x;
-    const int64_t L = Sh::S - 2 * h;
+    const int64_t L = seg_valid(Sh::S, h);
     const int64_t g0 = s * L - h;
     const int64_t nblk = (nb + W - 1) / W;
     Twiddles<Sh, -1> tw;
@@ -252,7 +257,7 @@ __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
     if (u >= total) return;
     const int64_t tb = u / nseg;
     const int64_t s = u - tb * nseg;
-    const int64_t L = Sh::S - 2 * h;
+    const int64_t L = seg_valid(Sh::S, h);
     const int iz0 = int(tb) * tpb;
     const int iz1 = min(nz, iz0 + tpb);
 
@@ -263,8 +268,8 @@ __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
     const float2 *__restrict__ sp = segspec + s * Sh::S;
 
     const int64_t kbase = s * L - h;  // plane column of segment point n is kbase + n
-    // columns [kbase + h, kend) of the plane come from this segment
-    const int nend = int(min(int64_t(Sh::S - h), nb - kbase));
+    // points [h, nend) of this segment are plane columns [s L, min(s L + L, nb))
+    const int nend = int(min(int64_t(h) + L, nb - kbase));
     const int sh = int(((kbase % 4) + 4) % 4);  // plane row offset of point 0 modulo 4
     for (int iz = iz0; iz < iz1; ++iz) {
         // Keep the per-point offsets inside the loop: hoisting the 32 addresses
@@ -277,10 +282,12 @@ __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
         for (int m = 0; m < Sh::R; ++m) v[m] = cmul(sp[to + Sh::NT * m], bz[to + Sh::NT * m]);
         fft_wg<Sh, +1>(v, lds, tw, t);
         float *__restrict__ row = plane + int64_t(iz) * nb + kbase;
-        uint8_t *__restrict__ qrow = codes + int64_t(iz) * nb + kbase;
+        uint8_t *__restrict__ qrow = codes + int64_t(iz) * (nb / 2);
         // Powers through LDS so that each thread stores 4 consecutive
         // points: point n sits at LDS index n + sh, which puts chunk c
-        // (indices 4c .. 4c+3) on a 16-byte boundary of the plane row.
+        // (indices 4c .. 4c+3) on a 16-byte boundary of the plane row, i.e.
+        // on two 2-bin blocks of the codes (L and s L are multiples of 4, so
+        // kept chunks are whole).
         float *__restrict__ lf = reinterpret_cast<float *>(lds);
 #pragma unroll
         for (int m = 0; m < Sh::R; ++m) lf[sh + to + Sh::NT * m] = cnorm(v[m]);
@@ -291,19 +298,7 @@ __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
             const float4 p4 = *reinterpret_cast<const float4 *>(lf + 4 * c);
             if (n0 >= h && n0 + 4 <= nend) {
                 *reinterpret_cast<float4 *>(row + n0) = p4;
-                *reinterpret_cast<uint32_t *>(qrow + n0) =
-                    uint32_t(power_code(p4.x, code_inv)) | (uint32_t(power_code(p4.y, code_inv)) << 8) |
-                    (uint32_t(power_code(p4.z, code_inv)) << 16) | (uint32_t(power_code(p4.w, code_inv)) << 24);
-            } else {
-                const float pe[4] = {p4.x, p4.y, p4.z, p4.w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int n = n0 + e;
-                    if (n >= h && n < nend) {
-                        row[n] = pe[e];
-                        qrow[n] = power_code(pe[e], code_inv);
-                    }
-                }
+                *reinterpret_cast<uint16_t *>(qrow + ((kbase + n0) >> 1)) = block_codes4(p4, code_inv);
             }
         }
         __syncthreads();  // the next transform writes lds
@@ -359,28 +354,31 @@ __device__ __forceinline__ void cell_sums(const float *__restrict__ P, int64_t n
     nested_sums<LEVELS>(v, s);
 }
 
-// Pass 1, the screen: every cell's sums on the code plane (see power_code).
-// A cell's integer code sum is at least its power sum / delta, so a cell
-// whose code sums stay below T_l = floor(thr_l / delta (1 - 1e-5)) at every
-// level cannot reach any threshold.  Cells that may ("flagged" cells) are
-// listed per group of 16 columns of one row: a group record holds the row,
-// the group, a 16-bit mask of its flagged cells and the index of its first
-// flagged cell in the cell arrays; group_map[iz][m] holds the record index of
-// group (m, iz).  Map entries are written only for flagged groups and are
-// trusted only when the record they point to names the same group, so the
+// Pass 1, the screen, on the codes of 2-bin blocks (see block_code): a code
+// is at least P / delta for both bins of its block, so for the block of bins
+// 2b, 2b + 1 of row iz, sum_j max(codes of the blocks holding c_j(2b) and
+// c_j(2b + 1) in row r_j) is at least each bin's power sum / delta.  A block
+// whose bounds stay below T_l = floor(thr_l / delta (1 - 1e-5)) at every level
+// holds no bin that can reach a threshold.  The others ("flagged") are listed
+// twice: as block entries (column pair, row), whose bins 2e and 2e + 1 are the
+// cell indices of entry e, and per group of 32 columns of one row (a record
+// with the row, the group, a 16-bit mask of its flagged blocks and its first
+// cell index; group_map[iz][m] holds the record index of group (m, iz)) for
+// the neighbour lookups.  Map entries are written only for flagged groups and
+// are trusted only when the record they point to names the same group, so the
 // map needs no clearing between searches.
 //
-// A lane owns the 16 consecutive columns k = 16 m + i (i < 16) of a row.
-// Since 16 m j is a multiple of 16, fraction j of column 16 m + i is
-// j m + c_j(i): the 16 codes of fraction j sit in bytes [j m, j m + c_j(15)]
-// of row r_j, at compile-time offsets c_j(i) from j m.  Cells 2p and 2p+1
-// share one 32-bit register (p < 8), one per 16-bit half: a sum of at most 16
-// codes (<= 4080) never carries into the upper half, and a half reaches
-// level l iff sum + 0x8000 - T_l sets its bit 15.  All loads of a row are
-// independent of each other and issued together.
+// A lane owns the 16 blocks 16 m + beta (32 columns) of a row.  Fraction j of
+// bin 2 (16 m + beta) + i lies in block j m + floor((2 j beta + j i + 8) / 32):
+// the 16 blocks' codes of fraction j sit in bytes [j m, j m + span) of row r_j
+// at compile-time offsets.  Blocks 2p and 2p+1 share one 32-bit register
+// (p < 8), one per 16-bit half: a sum of at most 16 codes (<= 4080) never
+// carries into the upper half, and a half reaches level l iff
+// sum + 0x8000 - T_l sets its bit 15.  All loads of a row are independent of
+// each other and issued together.
 constexpr int SC_TZ = 8;      // rows per wave
 constexpr int SC_WAVES = 4;   // waves per workgroup
-constexpr int SC_COLS = 16;   // columns per lane (one group)
+constexpr int SC_COLS = 32;   // columns per lane (one group)
 constexpr int SC_WAVE_COLS = 64 * SC_COLS;
 
 struct ScreenThr {
@@ -388,37 +386,59 @@ struct ScreenThr {
 };
 
 struct Group {
-    int32_t m;         // columns 16 m .. 16 m + 15
-    uint32_t iz_mask;  // row in bits 0..15, flagged cells in bits 16..31
-    uint32_t first;    // index of the first flagged cell in the cell arrays
+    int32_t m;         // columns 32 m .. 32 m + 31
+    uint32_t iz_mask;  // row in bits 0..15, flagged 2-column blocks in bits 16..31
+    uint32_t first;    // cell index of the group's first flagged bin
     uint32_t pad;
 };
 
-// Counters (six 32-bit words, zeroed before the pass): candidates; overflow
-// flag; flagged cells (low word) and groups (high word) of one 64-bit counter,
-// so that a wave reserves both with one atomic.
-enum { CNT_CANDS = 0, CNT_OVERFLOW = 2, CNT_PAIR = 4 };
+// Counters (six 32-bit words, zeroed before the pass): candidates; exact
+// hits; overflow flag; (unused); flagged cells (low word) and groups (high
+// word) of one 64-bit counter, so that a wave reserves both with one atomic.
+enum { CNT_CANDS = 0, CNT_HITS = 1, CNT_OVERFLOW = 2, CNT_PAIR = 4 };
 
+__device__ __forceinline__ uint32_t cell_count(const uint32_t *cnt) { return cnt[CNT_PAIR]; }
 __device__ __forceinline__ uint32_t group_count(const uint32_t *cnt) { return cnt[CNT_PAIR + 1]; }
 
-// Byte layout of one fraction's 16 codes.
+// Byte layout of one fraction's 16 block codes.
 template <int J>
-struct FracBytes {
-    static constexpr int off(int i) { return (J * i + 8) >> 4; }          // c_j(i)
-    static constexpr int span = off(15) + 1;                              // bytes used
+struct FracBlocks {
+    static constexpr int lo(int b) { return (2 * J * b + 8) >> 5; }      // block of bin 2 b
+    static constexpr int hi(int b) { return (2 * J * b + J + 8) >> 5; }  // block of bin 2 b + 1
+    static constexpr int span = hi(15) + 1;                              // bytes used
     static constexpr int maxshift = J % 4 == 0 ? 0 : J % 2 == 0 ? 2 : 3;  // (j m) mod 4
-    static constexpr int nd = (maxshift + span + 3) / 4;                  // dwords loaded
-    static constexpr int nw = (span + 3) / 4;                             // aligned words
+    static constexpr int nd = (maxshift + span + 3) / 4;                 // dwords loaded
+    static constexpr int nw = (span + 3) / 4;                            // aligned words
 };
 
 // Level group of fraction j: the level that first adds it (16 -> 0, 8 -> 1,
 // 4 and 12 -> 2, 2 mod 4 -> 3, odd -> 4).
 constexpr int frac_level(int j) { return j == 16 ? 0 : j % 2 ? 4 : j % 4 ? 3 : j % 8 ? 2 : 1; }
 
-// Add the 8 packed pairs of fraction J (lane's group m of row qrow) to acc.
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// Per-half maximum of two pairs of 16-bit values.
+__device__ __forceinline__ uint32_t max_u16x2(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t,
+                              __builtin_elementwise_max(__builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b)));
+}
+
+// Bytes A and C of the aligned words w (C >> 2 is A >> 2 or one more) in the
+// low bytes of the two 16-bit halves of the result.
+template <int A, int C, int NW>
+__device__ __forceinline__ uint32_t gather2(const uint32_t (&w)[NW]) {
+    constexpr int wa = A >> 2, wc = C >> 2;
+    static_assert(wc == wa || wc == wa + 1, "bytes in adjacent words");
+    // v_perm_b32 selector bytes: 0-3 pick bytes of the second source, 4-7
+    // bytes of the first, 0x0c gives zero.
+    constexpr uint32_t sel = uint32_t(A & 3) | 0x0c00u | (uint32_t((wc == wa ? 0 : 4) + (C & 3)) << 16) | 0x0c000000u;
+    return __builtin_amdgcn_perm(w[wc], w[wa], sel);
+}
+
+// Add fraction J's bounds of the lane's 8 block pairs (group m of row qrow) to acc.
 template <int J>
 __device__ __forceinline__ void add_fraction(const uint8_t *__restrict__ qrow, int64_t m, uint32_t (&acc)[8]) {
-    using FB = FracBytes<J>;
+    using FB = FracBlocks<J>;
     const int64_t b = int64_t(J) * m;  // first byte
     const uint32_t *__restrict__ src = reinterpret_cast<const uint32_t *>(qrow + (b & ~int64_t(3)));
     uint32_t d[FB::nd];
@@ -433,15 +453,13 @@ __device__ __forceinline__ void add_fraction(const uint8_t *__restrict__ qrow, i
 #pragma unroll
         for (int q = 0; q < FB::nw; ++q) w[q] = __builtin_amdgcn_alignbyte(d[q + 1 < FB::nd ? q + 1 : q], d[q], sh);
     }
-#pragma unroll
-    for (int p = 0; p < 8; ++p) {
-        const int a = FB::off(2 * p), c = FB::off(2 * p + 1);
-        const int wa = a >> 2, wc = c >> 2;
-        // v_perm_b32 selector bytes: 0-3 pick bytes of the second source,
-        // 4-7 bytes of the first, 0x0c gives zero.
-        const uint32_t sel = uint32_t(a & 3) | 0x0c00u | (uint32_t((wc == wa ? 0 : 4) + (c & 3)) << 16) | 0x0c000000u;
-        acc[p] += __builtin_amdgcn_perm(w[wc], w[wa], sel);
-    }
+    static_for<0, 8>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int l0 = FB::lo(2 * p), l1 = FB::lo(2 * p + 1), h0 = FB::hi(2 * p), h1 = FB::hi(2 * p + 1);
+        uint32_t v = gather2<l0, l1>(w);
+        if constexpr (h0 != l0 || h1 != l1) v = max_u16x2(v, gather2<h0, h1>(w));
+        acc[p] += v;
+    });
 }
 
 // Inclusive prefix sum over the wave.
@@ -457,16 +475,18 @@ __device__ __forceinline__ uint32_t wave_scan(uint32_t x, int lane) {
 template <int LEVELS>
 __global__ __launch_bounds__(64 * SC_WAVES) void k_screen(const uint8_t *__restrict__ Q, int nz, int64_t nb,
                                                           int izc, ScreenThr T, Group *__restrict__ groups,
-                                                          uint32_t *__restrict__ group_map, uint32_t *__restrict__ cnt,
-                                                          uint32_t group_cap, uint32_t cell_cap) {
+                                                          uint2 *__restrict__ blocks, uint32_t *__restrict__ group_map,
+                                                          uint32_t *__restrict__ cnt, uint32_t group_cap,
+                                                          uint32_t cell_cap) {
     // Row masks of the wave, kept until its records are written.
     __shared__ uint32_t rowmask_lds[SC_WAVES][SC_TZ][64];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    // a workgroup covers SC_WAVES * 1024 columns and SC_TZ rows
+    // a workgroup covers SC_WAVES * 2048 columns and SC_TZ rows
     const int64_t m = (int64_t(blockIdx.x) * SC_WAVES + wave) * 64 + lane;  // column group
     const int iz0 = blockIdx.y * SC_TZ;
     const int64_t ngr = nb / SC_COLS;
+    const int64_t qlen = nb / 2;  // codes per row
     const bool valid = m < ngr;
     if (!__any(valid) || iz0 >= nz) return;
     const int64_t mm = valid ? m : 0;  // lanes past the end read group 0 and report nothing
@@ -486,7 +506,7 @@ __global__ __launch_bounds__(64 * SC_WAVES) void k_screen(const uint8_t *__restr
         static_for<1, 17>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
             if constexpr (frac_used<LEVELS>(j))
-                add_fraction<j>(Q + int64_t(frac_row(izc, d, j)) * nb, mm, G[frac_level(j)]);
+                add_fraction<j>(Q + int64_t(frac_row(izc, d, j)) * qlen, mm, G[frac_level(j)]);
         });
         uint32_t mask = 0;
 #pragma unroll
@@ -503,16 +523,16 @@ __global__ __launch_bounds__(64 * SC_WAVES) void k_screen(const uint8_t *__restr
         }
         if (!valid) mask = 0;
         rowmask[64 * r] = mask;
-        mycells += __popc(mask);
+        mycells += 2u * __popc(mask);
         mygroups += mask != 0 ? 1u : 0u;
     }
-    // One group record per (lane, row) with flagged cells; a lane's records
+    // One group record per (lane, row) with flagged blocks; a lane's records
     // and cells get consecutive indices.  One atomic per wave reserves both
     // lists; crossing a capacity raises the overflow flag at once (so a count
     // that later wraps cannot hide it).  (Each lane reads back only its own
     // LDS words, so no barrier is needed.)
     if (!__any(mycells != 0)) return;
-    // cells (<= 16 SC_TZ 64) in the low half, groups in the high half
+    // cells (<= 32 SC_TZ 64 = 16384) in the low half, groups in the high half
     const uint32_t incl = wave_scan((mygroups << 16) | mycells, lane);
     const uint32_t total = __shfl(incl, 63);
     uint32_t cbase = 0, gbase = 0;
@@ -530,14 +550,19 @@ __global__ __launch_bounds__(64 * SC_WAVES) void k_screen(const uint8_t *__restr
     for (int r = 0; r < SC_TZ; ++r) {
         const uint32_t mask = rowmask[64 * r];
         if (mask == 0) continue;
-        const uint32_t ncell = __popc(mask);
+        const uint32_t ncell = 2u * __popc(mask);
+        const int iz = iz0 + r;
+        const bool fits = uint64_t(first) + ncell <= cell_cap;
         // every record below min(count, group_cap) is written, with no cells
         // when they do not fit (the overflow flag reports the loss)
         if (g < group_cap) {
-            const bool fits = uint64_t(first) + ncell <= cell_cap;
-            const int iz = iz0 + r;
             groups[g] = Group{int32_t(m), uint32_t(iz) | ((fits ? mask : 0u) << 16), first, 0u};
             if (fits) group_map[int64_t(iz) * ngr + m] = g;
+        }
+        if (fits) {
+            uint32_t e = first >> 1;
+            for (uint32_t bm = mask; bm; bm &= bm - 1u, ++e)
+                blocks[e] = make_uint2(uint32_t(m * (SC_COLS / 2) + __ffs(bm) - 1), uint32_t(iz));
         }
         ++g;
         first += ncell;
@@ -546,78 +571,94 @@ __global__ __launch_bounds__(64 * SC_WAVES) void k_screen(const uint8_t *__restr
 
 constexpr int SUM_STRIDE = 5;  // floats per flagged cell in the sums array
 
-// A record below the group count was written by this search; the range test
-// only guards against counts that wrapped after an overflow.
-__device__ __forceinline__ bool group_ok(const Group &r, int nz, int64_t nb, uint32_t cell_cap) {
-    return r.m >= 0 && int64_t(r.m) < nb / SC_COLS && int(r.iz_mask & 0xffffu) < nz &&
-           uint64_t(r.first) + uint32_t(__popc(r.iz_mask >> 16)) <= cell_cap;
+// Cell index of bin i (< 32) of a group, when its block is flagged.
+__device__ __forceinline__ bool cell_flagged(const Group &r, int i) { return (r.iz_mask >> (16 + (i >> 1))) & 1u; }
+__device__ __forceinline__ uint32_t cell_index(const Group &r, int i) {
+    const uint32_t bm = r.iz_mask >> 16;
+    return r.first + 2u * uint32_t(__popc(bm & ((1u << (i >> 1)) - 1u))) + uint32_t(i & 1);
 }
 
-// Pass 2: the exact FP32 sums of every flagged cell (16 lanes per group,
-// lane i on column 16 m + i), loaded from the plane in the one summation
-// order of nested_sums.
+// Pass 2, one lane per flagged cell: its exact FP32 sums, loaded from the
+// plane in the one summation order of nested_sums; cells reaching a threshold
+// at some level go to the hit list (one atomic per wave).
 template <int LEVELS>
-__global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int nz, int64_t nb, int izc,
-                                               const Group *__restrict__ groups, const uint32_t *__restrict__ cnt,
-                                               uint32_t group_cap, uint32_t cell_cap, float *__restrict__ sums) {
-    const uint32_t ng = min(group_count(cnt), group_cap);
-    const int i = threadIdx.x & 15;
-    for (uint32_t g = (blockIdx.x * blockDim.x + threadIdx.x) >> 4; g < ng; g += (gridDim.x * blockDim.x) >> 4) {
-        const Group r = groups[g];
-        const uint32_t mask = r.iz_mask >> 16;
-        if (!((mask >> i) & 1u) || !group_ok(r, nz, nb, cell_cap)) continue;
-        float s[5];
-        cell_sums<LEVELS>(P, nb, izc, int(r.iz_mask & 0xffffu), r.m * SC_COLS + i, s);
-        float *__restrict__ o = sums + int64_t(r.first + __popc(mask & ((1u << i) - 1u))) * SUM_STRIDE;
+__global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int nz, int64_t nb, int izc, Thr thr,
+                                               const uint2 *__restrict__ blocks, uint32_t *__restrict__ cnt,
+                                               uint32_t cell_cap, float *__restrict__ sums,
+                                               uint32_t *__restrict__ hits) {
+    const uint32_t nc = min(cell_count(cnt), cell_cap);
+    const int lane = threadIdx.x & 63;
+    const uint32_t stride = gridDim.x * blockDim.x;
+    // whole waves iterate together so that the appends stay wave-wide
+    for (uint32_t base = blockIdx.x * blockDim.x + (threadIdx.x & ~63u); base < nc; base += stride) {
+        const uint32_t c = base + lane;
+        bool hit = false;
+        if (c < nc) {
+            const uint2 e = blocks[c >> 1];
+            const int64_t k = 2 * int64_t(e.x) + (c & 1);
+            const int iz = int(e.y);
+            if (k < nb && iz < nz) {  // guards against entries of an overflowed list
+                float s[5];
+                cell_sums<LEVELS>(P, nb, izc, iz, int(k), s);
+                float *__restrict__ o = sums + int64_t(c) * SUM_STRIDE;
 #pragma unroll
-        for (int l = 0; l <= LEVELS; ++l) o[l] = s[l];
+                for (int l = 0; l <= LEVELS; ++l) {
+                    o[l] = s[l];
+                    hit = hit || s[l] >= thr.v[l];
+                }
+            }
+        }
+        const uint64_t ballot = __ballot(hit);
+        if (!ballot) continue;
+        uint32_t hb = 0;
+        if (lane == 0) hb = atomicAdd(cnt + CNT_HITS, uint32_t(__popcll(ballot)));
+        hb = __shfl(hb, 0);
+        if (hit) hits[hb + uint32_t(__popcll(ballot & ((uint64_t(1) << lane) - 1)))] = c;
     }
 }
 
-// Pass 3: thresholds and 3x3 local maxima on the exact sums (16 lanes per
-// group).  A cell keeps a level when its sum reaches the threshold and is
-// strictly greater than the neighbours earlier in row-major (iz, k) order and
-// at least equal to the later ones; neighbours outside the plane are ignored.
-// A neighbour that was not flagged has sums below every threshold, hence
-// below the cell's, and is beaten without being looked at.  The 8
-// neighbours' lookups (map entry, record, sums) are issued side by side.
+// Pass 3, one lane per hit: the 3x3 local maximum at every level the cell
+// reaches.  A cell keeps a level when it is strictly greater than the
+// neighbours earlier in row-major (iz, k) order and at least equal to the
+// later ones; neighbours outside the plane are ignored.  A neighbour that was
+// not flagged has sums below every threshold, hence below the cell's, and is
+// beaten without being looked at; the others are found through the group map
+// (map entry, record, sums, issued side by side for the 8 neighbours).
 template <int LEVELS>
 __global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, const Group *__restrict__ groups,
-                                               const uint32_t *__restrict__ group_map, const float *__restrict__ sums,
+                                               const uint32_t *__restrict__ group_map, const uint2 *__restrict__ blocks,
+                                               const float *__restrict__ sums, const uint32_t *__restrict__ hits,
                                                uint32_t *__restrict__ cnt, uint32_t group_cap, uint32_t cell_cap,
                                                DevCand *__restrict__ cands, uint32_t cap) {
     __shared__ uint32_t wsum[2][4];  // per-wave candidate counts, by iteration parity
     __shared__ uint32_t wgbase[2];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int i = lane & 15;
+    const uint32_t nh = cnt[CNT_HITS];
     const uint32_t ng = min(group_count(cnt), group_cap);
     const int64_t ngr = nb / SC_COLS;
-    // the workgroup iterates as a whole (16 groups per step) so that one
+    // the workgroup iterates as a whole (256 hits per step) so that one
     // atomic per step reserves the slots of all its candidates
     int par = 0;
-    for (uint32_t gw = blockIdx.x * 16u; gw < ng; gw += gridDim.x * 16u, par ^= 1) {
-        const uint32_t g = gw + uint32_t(threadIdx.x >> 4);
+    for (uint32_t hw = blockIdx.x * blockDim.x; hw < nh; hw += gridDim.x * blockDim.x, par ^= 1) {
+        const uint32_t hidx = hw + threadIdx.x;
         uint32_t lmask = 0;  // levels still alive
-        int64_t m = 0;
+        int64_t k = 0;
         int iz = 0;
         float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-        if (g < ng) {
-            const Group r = groups[g];
-            const uint32_t cmask = r.iz_mask >> 16;
-            if (((cmask >> i) & 1u) && group_ok(r, nz, nb, cell_cap)) {
-                iz = int(r.iz_mask & 0xffffu);
-                m = r.m;
-                const float *__restrict__ o = sums + int64_t(r.first + __popc(cmask & ((1u << i) - 1u))) * SUM_STRIDE;
+        if (hidx < nh) {
+            const uint32_t c = hits[hidx];
+            const uint2 e = blocks[c >> 1];
+            k = 2 * int64_t(e.x) + (c & 1);
+            iz = int(e.y);
+            const float *__restrict__ o = sums + int64_t(c) * SUM_STRIDE;
 #pragma unroll
-                for (int l = 0; l <= LEVELS; ++l) {
-                    s[l] = o[l];
-                    if (s[l] >= thr.v[l]) lmask |= 1u << l;
-                }
+            for (int l = 0; l <= LEVELS; ++l) {
+                s[l] = o[l];
+                if (s[l] >= thr.v[l]) lmask |= 1u << l;
             }
         }
         if (lmask != 0) {
-            const int64_t k = m * SC_COLS + i;
             // neighbour n = 3 (di + 1) + (dk + 1), n != 4
             uint32_t gi[9];
 #pragma unroll
@@ -628,7 +669,7 @@ __global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, cons
                 const int iz2 = iz + di;
                 const int64_t k2 = k + dk;
                 if (iz2 < 0 || iz2 >= nz || k2 < 0 || k2 >= nb) continue;
-                gi[n] = group_map[int64_t(iz2) * ngr + (k2 >> 4)];
+                gi[n] = group_map[int64_t(iz2) * ngr + k2 / SC_COLS];
             }
             Group rn[9];
 #pragma unroll
@@ -642,16 +683,14 @@ __global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, cons
             for (int n = 0; n < 9; ++n) {
                 const int di = n / 3 - 1, dk = n % 3 - 1;
                 const int64_t k2 = k + dk;
-                const int i2 = int(k2 & 15);
-                const uint32_t cm2 = rn[n].iz_mask >> 16;
-                use[n] = gi[n] < ng && int64_t(rn[n].m) == (k2 >> 4) &&
-                         (rn[n].iz_mask & 0xffffu) == uint32_t(iz + di) && ((cm2 >> i2) & 1u) &&
-                         uint64_t(rn[n].first) + uint32_t(__popc(cm2)) <= cell_cap;
+                const int i2 = int(k2 % SC_COLS);
+                use[n] = gi[n] < ng && int64_t(rn[n].m) == k2 / SC_COLS &&
+                         (rn[n].iz_mask & 0xffffu) == uint32_t(iz + di) && cell_flagged(rn[n], i2) &&
+                         uint64_t(rn[n].first) + 2u * uint32_t(__popc(rn[n].iz_mask >> 16)) <= cell_cap;
 #pragma unroll
                 for (int l = 0; l <= LEVELS; ++l) sn[n][l] = 0.f;
                 if (use[n]) {
-                    const float *__restrict__ o2 =
-                        sums + int64_t(rn[n].first + __popc(cm2 & ((1u << i2) - 1u))) * SUM_STRIDE;
+                    const float *__restrict__ o2 = sums + int64_t(cell_index(rn[n], i2)) * SUM_STRIDE;
 #pragma unroll
                     for (int l = 0; l <= LEVELS; ++l) sn[n][l] = o2[l];
                 }
@@ -667,8 +706,8 @@ __global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, cons
                 }
             }
         }
-        const uint32_t nc = __popc(lmask);
-        const uint32_t incl = wave_scan(nc, lane);
+        const uint32_t ncand = __popc(lmask);
+        const uint32_t incl = wave_scan(ncand, lane);
         if (lane == 63) wsum[par][wave] = incl;
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -676,13 +715,12 @@ __global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, cons
             wgbase[par] = tot ? atomicAdd(cnt + CNT_CANDS, tot) : 0u;
         }
         __syncthreads();
-        uint32_t slot = wgbase[par] + incl - nc;
+        uint32_t slot = wgbase[par] + incl - ncand;
         for (int w = 0; w < wave; ++w) slot += wsum[par][w];
-        const int kk = int(m * SC_COLS + i);
 #pragma unroll
         for (int l = 0; l <= LEVELS; ++l) {
             if ((lmask >> l) & 1u) {
-                if (slot < cap) cands[slot] = DevCand{kk, iz, 1 << l, s[l]};
+                if (slot < cap) cands[slot] = DevCand{int32_t(k), iz, 1 << l, s[l]};
                 ++slot;
             }
         }
@@ -805,6 +843,7 @@ hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, i
 
 size_t harmsum_scratch_bytes(int nz, int64_t nb, uint32_t cell_cap, uint32_t group_cap) {
     return size_t(group_cap) * sizeof(Group) + size_t(cell_cap) * SUM_STRIDE * sizeof(float) +
+           size_t((cell_cap + 1) / 2) * sizeof(uint2) + size_t(cell_cap) * sizeof(uint32_t) +
            size_t(nz) * size_t(nb / SC_COLS) * sizeof(uint32_t);
 }
 
@@ -822,19 +861,22 @@ hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int6
         thr.v[l] = thr_host[l];
         T.k[l] = (0x8000u - code_thr[l]) * 0x10001u;
     }
+    cell_cap &= ~1u;  // whole blocks
     Group *groups = static_cast<Group *>(scratch);
     float *sums = reinterpret_cast<float *>(groups + group_cap);
-    uint32_t *group_map = reinterpret_cast<uint32_t *>(sums + size_t(cell_cap) * SUM_STRIDE);
+    uint2 *blocks = reinterpret_cast<uint2 *>(sums + size_t(cell_cap) * SUM_STRIDE);
+    uint32_t *hits = reinterpret_cast<uint32_t *>(blocks + cell_cap / 2);
+    uint32_t *group_map = hits + cell_cap;
     const int64_t rows = SC_TZ, cols = int64_t(SC_WAVE_COLS) * SC_WAVES;
     const dim3 grid1(unsigned((nb + cols - 1) / cols), unsigned((nz + rows - 1) / rows));
     const unsigned grid2 = 2048;
 #define CALL(LV)                                                                                                   \
-    hipLaunchKernelGGL((k_screen<LV>), grid1, dim3(64 * SC_WAVES), 0, st, codes, nz, nb, izc, T, groups, group_map, \
-                       count, group_cap, cell_cap);                                                               \
-    hipLaunchKernelGGL((k_exact<LV>), dim3(grid2), dim3(256), 0, st, plane, nz, nb, izc, groups, count, group_cap,  \
-                       cell_cap, sums);                                                                           \
-    hipLaunchKernelGGL((k_peaks<LV>), dim3(grid2), dim3(256), 0, st, nz, nb, thr, groups, group_map, sums, count,   \
-                       group_cap, cell_cap, cands, cap);
+    hipLaunchKernelGGL((k_screen<LV>), grid1, dim3(64 * SC_WAVES), 0, st, codes, nz, nb, izc, T, groups, blocks,    \
+                       group_map, count, group_cap, cell_cap);                                                     \
+    hipLaunchKernelGGL((k_exact<LV>), dim3(grid2), dim3(256), 0, st, plane, nz, nb, izc, thr, blocks, count,        \
+                       cell_cap, sums, hits);                                                                     \
+    hipLaunchKernelGGL((k_peaks<LV>), dim3(grid2), dim3(256), 0, st, nz, nb, thr, groups, group_map, blocks, sums,  \
+                       hits, count, group_cap, cell_cap, cands, cap);
     switch (levels) {
         case 0: CALL(0); break;
         case 1: CALL(1); break;

@@ -36,8 +36,9 @@ hipError_t launch_unpack_median(const float2 *Z, int64_t nsamp, float2 *X, doubl
 hipError_t launch_median(const float2 *X, int64_t nb, double *med, int W, hipStream_t st);
 
 // Segment spectra: seg s = DFT_S of Xhat[s L - h + n], n in [0, S), where
-// Xhat = X sqrt(ln2 / m(k)) (m interpolated between block medians in FP64;
-// med == nullptr means X is already normalised); zero outside [0, nb).
+// L = (S - 2h) rounded down to a multiple of 4, Xhat = X sqrt(ln2 / m(k)) (m
+// interpolated between block medians in FP64; med == nullptr means X is
+// already normalised); zero outside [0, nb).
 hipError_t launch_segfft(const float2 *X, const double *med, int W, int64_t nb, int log2s, int h,
                          int64_t nseg, float2 *segspec, hipStream_t st);
 
@@ -46,9 +47,9 @@ hipError_t launch_normalise(const float2 *X, const double *med, int W, int64_t n
 
 // Fused correlation: for each segment s and template iz,
 //   y = IDFT_S(segspec[s] * bank[iz]) (unnormalised; bank carries 1/S),
-//   plane[iz][s L + n - h] = |y[n]|^2 for n in [h, S - h), inside [0, nb),
-// and beside it the screening code plane (nz x nb bytes)
-//   codes[iz][k] = min(255, ceil(plane[iz][k] * code_inv)).
+//   plane[iz][s L + n - h] = |y[n]|^2 for n in [h, h + L), inside [0, nb),
+// and beside it the screening codes of 2-bin blocks (nz x nb/2 bytes)
+//   codes[iz][b] = max_{k in {2b, 2b + 1}} min(255, ceil(plane[iz][k] * code_inv)).
 hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, int tpb, int64_t nb,
                             int log2s, int h, int64_t nseg, float *plane, uint8_t *codes, float code_inv,
                             hipStream_t st);
@@ -66,23 +67,26 @@ void build_gemm_bank(const double *taps, int nz, int h, bool bf16, void *out);
 // Xhat = X sqrt(ln2 / m(k)) (or X when med is NULL) as 16-bit (Re, Im) pairs.
 hipError_t launch_lowp_spectrum(const float2 *X, const double *med, int W, int64_t nb, bool bf16, uint32_t *out,
                                 hipStream_t st);
-// plane[iz][k] = |sum_q Xhat[k - q] T_iz[q]|^2 and its screening codes (as
-// launch_correlate), over `workgroups` persistent workgroups.  nb % 4 == 0.
+// plane[iz][k] = |sum_q Xhat[k - q] T_iz[q]|^2 and its block screening codes
+// (as launch_correlate), over `workgroups` persistent workgroups.  nb % 4 == 0.
 hipError_t launch_corr_gemm(const uint32_t *xl, int64_t nb, int h, const void *bank, int nz, bool bf16,
                             int workgroups, float *plane, uint8_t *codes, float code_inv, hipStream_t st);
 
 // Harmonic sums over 1..nharm_max harmonics, thresholds and 3x3 local
-// maxima.  thr[i] is the threshold of 2^i harmonics, code_thr[i] (<= 0x8000)
-// the screen's threshold in code units: it must not exceed the code sum of any
-// cell whose exact FP32 sum reaches thr[i].  Three passes: a screen of every
-// cell's code sums that lists the cells which may reach a threshold, their
-// exact sums from the plane, and the threshold and neighbour tests on those.
-// scratch: harmsum_scratch_bytes(nz, nb, cell_cap, group_cap) bytes, for at
-// most cell_cap listed cells in group_cap groups of 16 columns.  count[0..5]
-// must start at 0: candidates are appended to cands (capacity cap) through
-// count[0]; count[4] and count[5] count listed cells and groups; count[2] is
-// set to 1 if either list overflowed (the candidates are then incomplete).
-// nb must be a multiple of 16, nz at most 65535.
+// maxima.  codes: the 2-bin block codes written beside the plane (nz x nb/2).
+// thr[i] is the threshold of 2^i harmonics, code_thr[i] (<= 0x8000) the
+// screen's threshold in code units: it must not exceed the code sum of any
+// bin whose exact FP32 sum reaches thr[i].  Three passes: a screen of every
+// 2-bin block's bound that lists the blocks which may hold a bin reaching a
+// threshold, the exact sums of their bins from the plane (listing the bins
+// that reach one), and the neighbour test of those.  scratch:
+// harmsum_scratch_bytes(nz, nb, cell_cap, group_cap) bytes, for at most
+// cell_cap listed bins in group_cap groups of 32 columns.  count[0..5] must
+// start at 0: candidates are appended to cands (capacity cap) through
+// count[0]; count[1] counts bins reaching a threshold, count[4] and count[5]
+// listed bins and groups; count[2] is set to 1 if a list overflowed (the
+// candidates are then incomplete).  nb must be a multiple of 32, nz at most
+// 65535.
 size_t harmsum_scratch_bytes(int nz, int64_t nb, uint32_t cell_cap, uint32_t group_cap);
 hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int64_t nb, int izc, int nharm_max,
                           const float *thr_host, const uint32_t *code_thr, void *scratch, uint32_t cell_cap,

@@ -316,7 +316,7 @@ def test_ska_trial_sampled(gpu_lib):
     iz = rng.integers(0, bank.nz, 3000)
     k = rng.integers(0, n // 2, 3000)
     # plus segment edges and the ragged end of the spectrum
-    L = seg - 2 * h
+    L = (seg - 2 * h) & ~3  # valid bins per segment (a multiple of 4)
     edge_k = np.concatenate([np.arange(0, 3), L - 1 + np.arange(3), 77 * L + np.arange(-2, 2), n // 2 - 3 + np.arange(3)])
     iz = np.concatenate([iz, rng.integers(0, bank.nz, edge_k.shape[0])])
     k = np.concatenate([k, edge_k])
