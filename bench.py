@@ -69,9 +69,10 @@ def correlate_flops(nseg: int, nz: int, S: int, L: int) -> float:
 
 
 def correlate_bytes(nseg: int, nz: int, S: int, nb: int) -> float:
-    """Algorithmic HBM bytes of one fused-correlation launch: the plane written
-    once (4 nz Nb), the segment spectra (8 nseg S) and the bank (8 nz S) read once."""
-    return 4.0 * nz * nb + 8.0 * nseg * S + 8.0 * nz * S
+    """Algorithmic HBM bytes of one fused-correlation launch: the plane and its
+    2-bin block codes written once (4 nz Nb + nz Nb / 2), the segment spectra
+    (8 nseg S) and the bank (8 nz S) read once."""
+    return 4.0 * nz * nb + 0.5 * nz * nb + 8.0 * nseg * S + 8.0 * nz * S
 
 
 def read_traffic():
