@@ -14,7 +14,7 @@ namespace fdas {
 
 namespace {
 
-constexpr int RS_BLOCKS = 256;   // workgroups of the histogram and scatter passes
+constexpr int RS_BLOCKS = 128;   // workgroups of the histogram and scatter passes
 constexpr int RS_THREADS = 256;  // four waves
 constexpr int RS_DIGITS = 256;   // 8-bit digits
 

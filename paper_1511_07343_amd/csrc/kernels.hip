@@ -25,6 +25,10 @@ constexpr int corr_threads(int log2s) { return fft_threads(log2s); }
 // 8 XCDs on MI355X; workgroups are dispatched to XCDs round-robin by index.
 constexpr int kXcds = 8;
 
+// Plane stores bypass the L2 retention (streaming), so that they do not evict
+// the templates an XCD reuses across segments.
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+
 // Valid points per segment: S - 2h rounded down to a multiple of 4, so that
 // the correlation's 4-bin store chunks (and the 2-bin blocks of the screening
 // codes) never straddle two segments.
@@ -297,8 +301,9 @@ __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
             const int n0 = 4 * c - sh;
             const float4 p4 = *reinterpret_cast<const float4 *>(lf + 4 * c);
             if (n0 >= h && n0 + 4 <= nend) {
-                *reinterpret_cast<float4 *>(row + n0) = p4;
-                *reinterpret_cast<uint16_t *>(qrow + ((kbase + n0) >> 1)) = block_codes4(p4, code_inv);
+                __builtin_nontemporal_store(__builtin_bit_cast(f32x4v, p4), reinterpret_cast<f32x4v *>(row + n0));
+                __builtin_nontemporal_store(block_codes4(p4, code_inv),
+                                            reinterpret_cast<uint16_t *>(qrow + ((kbase + n0) >> 1)));
             }
         }
         __syncthreads();  // the next transform writes lds
