@@ -19,6 +19,7 @@ Prints one JSON line: the plain per-trial rate as ``value``, then
              included): saturated (a bounded number in flight) for
              throughput, and the first requests at their arrival times,
              compressed 10x, for p50/p99 latency;
+  template_sweep  the plain rate at 51, 101, 201 and 401 templates;
   precision  16 trials of 2^22 samples, 801 templates (z in [-400, 400],
              step 1): FP32 FFT correlation against the BF16 and FP16
              matrix-core correlators, with power error and candidate
@@ -211,6 +212,33 @@ def bench_served(fdas, bank, ring, requests: int, paced: int, speedup: float):
     return out
 
 
+def bench_template_sweep(fdas, xs, pinned, steps: int = 8):
+    """Plain per-trial rate against the number of templates (z in
+    [-zmax, zmax], step 2) at 2^23 samples, 8192-bin segments, 16 harmonics
+    (candidates into the same page-locked buffer as the plain loop)."""
+    import torch
+    out = []
+    for zmax in (50.0, 100.0, 200.0, 400.0):
+        bank = fdas.make_templates(zmax, DZ)
+        plan = fdas.Plan(bank, N, SEG, nharm_max=NHARM, sigma=SIGMA)
+        plan.search(xs[0], out=pinned)
+        torch.cuda.synchronize()
+        plan.enable_timing(True)
+        t0 = time.perf_counter()
+        for i in range(steps):
+            plan.search(xs[i % len(xs)], out=pinned)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        st, nt = plan.stage_times()
+        out.append({"templates": bank.nz, "value": round(1.0 / dt, 3), "unit": "DM trials/s",
+                    "correlate_ms": round(st["correlate"] / nt, 4),
+                    "harmonic_sum_ms": round(st["harmonic_sum"] / nt, 4),
+                    "realtime_multiple": round(1.0 / dt / (6000 / 530.0), 2)})
+        plan.close()
+        bank.close()
+    return out
+
+
 C5_ZMAX, C5_DZ, C5_N = 400.0, 1.0, 1 << 22
 
 
@@ -331,6 +359,7 @@ def main():
     ap.add_argument("--speedup", type=float, default=10.0, help="time compression of the paced replay")
     ap.add_argument("--precision-trials", type=int, default=16, help="trials of the precision comparison (0 = skip)")
     ap.add_argument("--precision-band", type=int, default=65536, help="oracle band of the precision comparison")
+    ap.add_argument("--sweep", type=int, default=1, help="template-count sweep 51/101/201/401 (0 = skip)")
     ap.add_argument("--cpu-bins", type=int, default=1 << 17, help="oracle sample width in bins (0 = skip)")
     ap.add_argument("--plain-only", action="store_true", help="only the plain per-trial loop (profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -377,7 +406,7 @@ def main():
     nseg = -(-nb // L)
     torch.cuda.synchronize()
 
-    out = fdas.pinned_candidates(1 << 22)  # page-locked record buffer, reused every step
+    out = pinned = fdas.pinned_candidates(1 << 22)  # page-locked record buffer, reused every step
     log(f"warmup {args.warmup}")
     for i in range(args.warmup):
         plan.search(xs[i % len(xs)], out=out)
@@ -420,6 +449,10 @@ def main():
                      "algorithmic_flops": flops, "launch_ms": round(corr_ms, 4),
                      "hbm_GBs": round(correlate_bytes(nseg, nz, SEG, nb) / (corr_ms * 1e-3) / 1e9, 1)},
     }
+
+    if extra and args.sweep:
+        log("template-count sweep")
+        out["template_sweep"] = bench_template_sweep(fdas, xs, pinned)
 
     if batch_host:
         bxs = [torch.from_numpy(x).to(dev) for x in batch_host]

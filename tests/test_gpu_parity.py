@@ -350,3 +350,63 @@ def test_ska_trial_sampled(gpu_lib):
         assert len(near) > 0, p
     plan.close()
     bank.close()
+
+
+def test_segment_length_invariance(gpu_lib):
+    """The overlap-save segment length changes only the rounding: S = 2048,
+    4096 and 8192 give the same plane (to 1e-4) and the same candidates as the
+    oracle's direct sum, and so as each other (2^17 samples, 101 templates,
+    16 harmonics)."""
+    t = synth.make_series(1 << 17, seed=31, pulsars=[synth.Pulsar(r=12000.2, z=-30.0, amp=0.06, nharm=6)])
+    orc = O.search(t.x, zmax=100.0, dz=2.0, sigma=5.5, nharm_max=16, keep_sums=True)
+    sets = []
+    for seg in (2048, 4096, 8192):
+        P, cands, n = _run(gpu_lib, t.x, 100.0, 2.0, seg, nharm_max=16, sigma=5.5)
+        worst, _, _ = plane_errors(P, orc.plane)
+        assert worst <= REL, (seg, worst)
+        rep = compare_candidates(cands, orc)
+        assert rep["ok"], (seg, {k: (v if not isinstance(v, list) else v[:10]) for k, v in rep.items()})
+        sets.append({(int(c["nharm"]), int(c["k"]), int(c["iz"])) for c in cands})
+    assert len(sets[0]) > 10
+    # each length matched the oracle up to its borderline cells, so the three
+    # sets can differ only there
+    o_keys = {(c.nharm, c.k, c.iz) for c in orc.candidates}
+    for a in sets[1:]:
+        assert len(a ^ sets[0]) <= len(a ^ o_keys) + len(sets[0] ^ o_keys)
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_random_configurations(gpu_lib, case):
+    """Seeded random shapes: length, segment, template range and step,
+    harmonics, threshold and median window, against the oracle."""
+    rng = np.random.default_rng(100 + case)
+    log2n = int(rng.integers(12, 17))
+    n = 1 << log2n
+    dz = float(rng.choice([0.5, 1.0, 2.0]))
+    zmax = dz * int(rng.integers(1, 21))
+    h = O.halfwidth(zmax)
+    segs = [s for s in (256, 512, 1024, 2048, 4096) if s >= 4 * h and s <= n // 2]
+    seg = int(rng.choice(segs))
+    nharm = int(rng.choice([1, 2, 4, 8, 16]))
+    sigma = float(rng.uniform(3.5, 6.0))
+    W = int(rng.choice([w for w in (64, 128, 256, 512) if w <= n // 2]))
+    p = synth.Pulsar(r=float(rng.uniform(100, n / 2 - 200)), z=float(rng.uniform(-zmax, zmax)),
+                     amp=float(rng.uniform(0.05, 0.2)), nharm=int(rng.integers(1, 4)))
+    t = synth.make_series(n, seed=200 + case, pulsars=[p])
+    P, cands, nf = _run(gpu_lib, t.x, zmax, dz, seg, nharm_max=nharm, sigma=sigma, median_window=W)
+    orc = O.search(t.x, zmax=zmax, dz=dz, sigma=sigma, nharm_max=nharm, W=W, keep_sums=True)
+    worst, _, _ = plane_errors(P, orc.plane)
+    cfg = dict(n=n, seg=seg, zmax=zmax, dz=dz, nharm=nharm, sigma=sigma, W=W)
+    assert worst <= REL, (cfg, worst)
+    rep = compare_candidates(cands, orc)
+    assert rep["ok"], (cfg, {k: (v if not isinstance(v, list) else v[:10]) for k, v in rep.items()})
+
+
+def test_device_memory_exhaustion_is_nomem(gpu_lib):
+    """A plan whose buffers cannot fit in device memory fails with NOMEM (and
+    leaves nothing allocated), rather than faulting later."""
+    bank = gpu_lib.make_templates(1200.0, 0.5)  # 4801 templates
+    with pytest.raises(gpu_lib.FdasError) as e:
+        gpu_lib.Plan(bank, 1 << 26, 8192)  # plane alone: 4801 x 2^25 x 4 B = 644 GB
+    assert e.value.status == -2
+    bank.close()
