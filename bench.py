@@ -19,6 +19,8 @@ Prints one JSON line: the plain per-trial rate as ``value``, then
              included): saturated (a bounded number in flight) for
              throughput, and the first requests at their arrival times,
              compressed 10x, for p50/p99 latency;
+  small      the 2^17-sample, 101-template single-tone configuration: per-call
+             latency (launch-bound);
   template_sweep  the plain rate at 51, 101, 201 and 401 templates;
   precision  16 trials of 2^22 samples, 801 templates (z in [-400, 400],
              step 1): FP32 FFT correlation against the BF16 and FP16
@@ -239,6 +241,31 @@ def bench_template_sweep(fdas, xs, pinned, steps: int = 8):
     return out
 
 
+def bench_small(fdas, steps: int = 200):
+    """The small plain configuration: 2^17 samples with one drifting tone,
+    101 templates, 2048-bin segments, one harmonic, 6 sigma (launch-bound:
+    latency per call, candidates to the host included)."""
+    import numpy as np
+    import torch
+    import synth
+    x = torch.from_numpy(synth.single_tone_series().x).cuda()
+    bank = fdas.make_templates(100.0, DZ)
+    plan = fdas.Plan(bank, 1 << 17, 2048, nharm_max=1, sigma=SIGMA)
+    for _ in range(5):
+        plan.search(x)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        plan.search(x)
+        lat.append(time.perf_counter() - t0)
+    plan.close()
+    bank.close()
+    return {"value": round(1.0 / float(np.mean(lat)), 3), "unit": "DM trials/s", "calls": steps,
+            "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 4),
+                           "p99": round(1e3 * float(np.percentile(lat, 99)), 4)}}
+
+
 C5_ZMAX, C5_DZ, C5_N = 400.0, 1.0, 1 << 22
 
 
@@ -449,6 +476,10 @@ def main():
                      "algorithmic_flops": flops, "launch_ms": round(corr_ms, 4),
                      "hbm_GBs": round(correlate_bytes(nseg, nz, SEG, nb) / (corr_ms * 1e-3) / 1e9, 1)},
     }
+
+    if extra:
+        log("small configuration latency")
+        out["small"] = bench_small(fdas)
 
     if extra and args.sweep:
         log("template-count sweep")

@@ -122,14 +122,16 @@ __global__ __launch_bounds__(fft_threads(LOG2M2)) void k_r2c_rows(const float2 *
 }
 
 // ------------------------------------------------------ medians of |X|^2
-// Ascending bitonic sort of W (power of two) floats in LDS.
+// Ascending bitonic sort of W (power of two) floats in LDS.  Strides are
+// powers of two, so pair indices are formed with shifts and masks.
 __device__ void bitonic_sort_lds(float *s, int W) {
     const int t = threadIdx.x, nt = blockDim.x;
     for (int size = 2; size <= W; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        for (int lg = __ffs(size) - 2; lg >= 0; --lg) {
+            const int stride = 1 << lg;
             __syncthreads();
             for (int i = t; i < (W >> 1); i += nt) {
-                const int lo = 2 * stride * (i / stride) + (i % stride);
+                const int lo = ((i >> lg) << (lg + 1)) | (i & (stride - 1));  // 2 stride (i / stride) + i % stride
                 const int hi = lo + stride;
                 const bool asc = (lo & size) == 0;
                 const float a = s[lo], b = s[hi];
