@@ -7,7 +7,7 @@ Source: S. Dimoudi and W. Armour, "Pulsar Acceleration Searches on the GPU for
 the Square Kilometre Array" (arXiv:1511.07343).  Each function names the part
 of the paper it follows.  The paper leaves several points open (normalisation,
 template width, harmonic summing, thresholds, peak rule); the readings taken
-here are stated where they are used and collected in the design doc.
+here are stated where they are used.
 
 Every step is the plain definition, with no FFT-based correlation, no
 segmentation, no blocking:
@@ -20,6 +20,9 @@ segmentation, no blocking:
 5. ``harmonic_sum``    incoherent sums over 1/2/4/8/16 harmonics (reading).
 6. ``thresholds``      single-trial sigma threshold per harmonic count (reading).
 7. ``find_peaks``      threshold plus 3x3 local maximum (reading).
+8. ``interp_power``, ``refine``  Fourier interpolation of the correlation at
+                        fractional (r, z) and a pattern search around each
+                        candidate (an extension past the paper's method).
 
 Parity pins for each function live in tests/test_oracle_*.py.
 """
@@ -58,6 +61,11 @@ __all__ = [
     "Candidate",
     "SearchResult",
     "search",
+    "interp_power",
+    "interp_sum",
+    "refine_start",
+    "refine",
+    "refine_endpoints",
 ]
 
 LN2 = math.log(2.0)
@@ -442,3 +450,104 @@ def search(x=None, *, spectrum=None, normalised: bool = False, zmax: float, dz: 
                                    power=s, sigma=sigma_of(s, nh)))
     return SearchResult(plane=P, candidates=cands, thresholds=thr, spectrum=Xhat, zs=zs, h=h,
                         sums=sums)
+
+
+# --------------------------------------------------------------------------
+# 8. Fourier interpolation and candidate refinement (an extension past the
+#    paper's method: the response of Sec. 2 evaluated off the (k, z) grid)
+# --------------------------------------------------------------------------
+def interp_power(Xhat: np.ndarray, r: float, z: float, h: int) -> float:
+    """P(r, z): the correlation of Eq. (1) at a fractional frequency r (bins)
+    and any drift z, with the template built for that exact offset (reading).
+
+    The bins used are those within h of r, K(r) = {k : |r - k| <= h}; the
+    template is the conjugate response at offsets r - k, normalised over K(r):
+        Y = sum_{k in K(r)} Xhat[k] conj(A(r - k, z)) / sqrt(sum_{k in K(r)} |A(r - k, z)|^2)
+    with Xhat = 0 outside [0, nb), and P = |Y|^2.  At an integer r and a grid
+    z this is the plane cell of ``correlate``; for white unit-mean-power
+    noise P is unit-mean exponential at every (r, z).
+    """
+    nb = Xhat.shape[0]
+    k = np.arange(math.ceil(r - h), math.floor(r + h) + 1, dtype=np.int64)
+    a = template_response(r - k.astype(np.float64), float(z))
+    inside = (k >= 0) & (k < nb)
+    y = np.sum(Xhat[k[inside]] * np.conj(a[inside]))
+    return float(abs(y) ** 2 / np.sum(np.abs(a) ** 2))
+
+
+def interp_sum(Xhat: np.ndarray, r: float, z: float, nh: int, h: int) -> float:
+    """S(r, z) = sum_{j=1}^{nh} P(j r, j z): harmonic j of the fundamental
+    (r, z) taken at its exact frequency and drift (no rounding to cells)."""
+    return float(sum(interp_power(Xhat, j * r, j * z, h) for j in range(1, nh + 1)))
+
+
+def refine_start(k: int, iz: int, nh: int, dz: float, izc: int):
+    """Fundamental of a candidate cell: r = k / nh, z = ((iz - izc) dz) / nh."""
+    return k / nh, (float(iz - izc) * dz) / nh
+
+
+def _refine_level(Xhat, r, z, level, nh, dz, zmax, h):
+    """Values of the 8 neighbours of (r, z) at one level, in search order:
+    steps sr = 2^-level / nh, sz = (dz 2^-level) / nh; z-offset major, then
+    r-offset, each in -1, 0, +1 (the centre itself skipped).  Points whose top
+    harmonic drifts beyond the bank (|nh z| > zmax) are not candidates."""
+    sr = 2.0 ** -level / nh
+    sz = (dz * 2.0 ** -level) / nh
+    out = []
+    for b in (-1, 0, 1):
+        for a in (-1, 0, 1):
+            if a == 0 and b == 0:
+                continue
+            rr = r + a * sr
+            zz = z + b * sz
+            if abs(nh * zz) > zmax:
+                continue
+            out.append((rr, zz, interp_sum(Xhat, rr, zz, nh, h)))
+    return out
+
+
+def refine(Xhat: np.ndarray, k: int, iz: int, nh: int, *, zmax: float, dz: float, h: int,
+           levels: int):
+    """Pattern search for the largest S(r, z) around a candidate (reading).
+
+    Start at the candidate's fundamental; at each level l = 1 .. levels look
+    at the 8 neighbours at steps (2^-l / nh, dz 2^-l / nh) in the order of
+    ``_refine_level`` and move to the first one whose S is strictly larger
+    than every value seen before it on this level (the centre's included).
+    The steps halve per level, so the search can move up to one grid cell
+    of the fundamental and ends on a (2^-levels)-fraction of it.  Returns
+    (r, z, S, sigma) of the final point.
+    """
+    izc = int(round(zmax / dz))
+    r, z = refine_start(k, iz, nh, dz, izc)
+    best = interp_sum(Xhat, r, z, nh, h)
+    for level in range(1, levels + 1):
+        br, bz = r, z
+        for rr, zz, s in _refine_level(Xhat, r, z, level, nh, dz, zmax, h):
+            if s > best:
+                best, br, bz = s, rr, zz
+        r, z = br, bz
+    return r, z, best, sigma_of(best, nh)
+
+
+def refine_endpoints(Xhat: np.ndarray, k: int, iz: int, nh: int, *, zmax: float, dz: float, h: int,
+                     levels: int, tol, max_paths: int = 1024):
+    """Every end point the search of ``refine`` can reach when values within
+    tol(S) of a level's best count as ties (either may win in a different
+    rounding): a dict {(r, z): S}.  Used to check a result computed in lower
+    precision, where near-equal neighbours may be ordered differently."""
+    izc = int(round(zmax / dz))
+    r0, z0 = refine_start(k, iz, nh, dz, izc)
+    paths = [(r0, z0, interp_sum(Xhat, r0, z0, nh, h))]
+    for level in range(1, levels + 1):
+        nxt = {}
+        for r, z, s0 in paths:
+            pts = [(r, z, s0)] + _refine_level(Xhat, r, z, level, nh, dz, zmax, h)
+            top = max(p[2] for p in pts)
+            for rr, zz, s in pts:
+                if s >= top - tol(top):
+                    nxt[(rr, zz)] = s
+        if len(nxt) > max_paths:
+            raise RuntimeError("refine_endpoints: too many near-tied paths")
+        paths = [(rr, zz, s) for (rr, zz), s in nxt.items()]
+    return {(r, z): s for r, z, s in paths}
