@@ -21,6 +21,9 @@ Prints one JSON line: the plain per-trial rate as ``value``, then
              compressed 10x, for p50/p99 latency;
   small      the 2^17-sample, 101-template single-tone configuration: per-call
              latency (launch-bound);
+  refine     Fourier interpolation and candidate refinement: the 256 most
+             significant records of the trial refined by fdas_refine, and
+             the small configuration with every candidate refined;
   template_sweep  the plain rate at 51, 101, 201 and 401 templates;
   precision  16 trials of 2^22 samples, 801 templates (z in [-400, 400],
              step 1): FP32 FFT correlation against the BF16 and FP16
@@ -266,6 +269,56 @@ def bench_small(fdas, steps: int = 200):
                            "p99": round(1e3 * float(np.percentile(lat, 99)), 4)}}
 
 
+def bench_refine(fdas, plan, x, h: int, top: int = 256, levels: int = 6, reps: int = 5):
+    """Candidate refinement on the SKA-shaped trial: the `top` most significant
+    records of a plain search refined by fdas_refine (FP64 Fourier
+    interpolation, pattern search of `levels` levels), timed per call (H2D
+    and D2H of the records included); and the small configuration with every
+    candidate refined inside fdas_search."""
+    import numpy as np
+    import torch
+    import synth
+    cands, n = plan.search(x)
+    sel = cands[np.argsort(-cands["sigma"], kind="stable")[:top]]
+    plan.refine(sel, levels)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ref = plan.refine(sel, levels)
+    dt = (time.perf_counter() - t0) / reps
+    # response evaluations: (1 + 8 levels) points x nharm harmonics x ~2h + 1/2 offsets
+    evals = float(np.sum((1 + 8 * levels) * sel["nharm"].astype(np.float64) * (2 * h + 0.5)))
+    gain = ref["power"].astype(np.float64) / sel["power"].astype(np.float64)
+    out = {"records": int(len(sel)), "of": int(n), "levels": levels, "ms_per_call": round(1e3 * dt, 3),
+           "us_per_record": round(1e6 * dt / max(len(sel), 1), 2),
+           "response_evals_per_s": round(evals / dt, 1),
+           "power_gain": {"median": round(float(np.median(gain)), 4), "max": round(float(np.max(gain)), 4)}}
+    xs = torch.from_numpy(synth.single_tone_series().x).cuda()
+    bank = fdas.make_templates(100.0, DZ)
+    lat = {}
+    for lv in (0, levels):
+        p = fdas.Plan(bank, 1 << 17, 2048, nharm_max=1, sigma=SIGMA, refine_levels=lv)
+        for _ in range(5):
+            c, _n = p.search(xs)
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(50):
+            s0 = time.perf_counter()
+            c, _n = p.search(xs)
+            t.append(time.perf_counter() - s0)
+        lat[lv] = (float(np.percentile(t, 50)), c)
+        p.close()
+    bank.close()
+    best = lat[levels][1][np.argmax(lat[levels][1]["power"])]
+    out["small_in_search"] = {"candidates": int(len(lat[levels][1])),
+                              "latency_p50_ms": {"plain": round(1e3 * lat[0][0], 4),
+                                                 "refined": round(1e3 * lat[levels][0], 4)},
+                              "strongest": {"r": float(best["r"]), "z": float(best["z"]),
+                                            "power": float(best["power"]),
+                                            "grid_power": float(np.max(lat[0][1]["power"]))}}
+    return out
+
+
 C5_ZMAX, C5_DZ, C5_N = 400.0, 1.0, 1 << 22
 
 
@@ -480,6 +533,8 @@ def main():
     if extra:
         log("small configuration latency")
         out["small"] = bench_small(fdas)
+        log("candidate refinement")
+        out["refine"] = bench_refine(fdas, plan, xs[0], h)
 
     if extra and args.sweep:
         log("template-count sweep")

@@ -80,7 +80,26 @@ typedef struct fdas_opts {
     int64_t cand_capacity;       /* device candidate buffer entries (default 1<<20)          */
     int32_t templates_per_block; /* templates per correlation workgroup, 0 = automatic       */
     int32_t correlator;          /* FDAS_CORR_FFT_F32 (default) or a matrix form, see below   */
+    int32_t refine_levels;       /* candidate refinement levels, 0 = off (default), <= 20     */
 } fdas_opts;
+
+/* Candidate refinement (refine_levels > 0), an extension past the paper's
+ * method: Fourier interpolation of the correlation at fractional frequency
+ * and drift.  The response A(q, z) of Sec. 2 is evaluated at the exact
+ * offsets r - k of the bins k with |r - k| <= h, so that
+ *   P(r, z) = |sum_k Xhat[k] conj(A(r - k, z))|^2 / sum_k |A(r - k, z)|^2
+ * (Xhat zero outside [0, Nb)); at integer r and a bank z it is the plane
+ * cell.  S(r, z) = sum_{j=1}^{nharm} P(j r, j z) sums the harmonics at their
+ * exact positions.  Each candidate's fundamental then moves by a pattern
+ * search: from r = k / nharm, z = ((iz - izc) dz) / nharm (izc = zmax / dz),
+ * level l = 1 .. refine_levels looks at the 8 neighbours at steps
+ * (2^-l / nharm, dz 2^-l / nharm), z offset major then r offset, each -1, 0,
+ * +1, and moves to the first that beats every earlier value of the level,
+ * the centre's included; a neighbour with |nharm z| > zmax is skipped.  The
+ * record's r, z, power (= S) and sigma (of S, nharm harmonics) describe the
+ * final point; k, iz and nharm still name the plane cell found.  FP64, on
+ * the device, before the records are copied; its time is stage 5 of the
+ * stage timers. */
 
 /* Correlator of a plan.  FDAS_CORR_FFT_F32: overlap-save segments, FP32 DFTs
  * (Sec. 2, Sec. 4 steps 3-7).  FDAS_CORR_GEMM_BF16 / FDAS_CORR_GEMM_F16:
@@ -162,9 +181,10 @@ fdas_status fdas_search(fdas_plan_t *plan, int32_t in_kind, const void *in_dev,
  * event pair around each stage on the stream the stage runs on and adds the
  * elapsed times (ms) into per-stage totals: 0 real-input DFT, 1 unpack and
  * block medians, 2 segment DFTs, 3 fused multiply / inverse DFT / power,
- * 4 harmonic sum and peaks.  fdas_plan_stage_times copies the FDAS_NSTAGES
+ * 4 harmonic sum, peaks and candidate ordering, 5 candidate refinement
+ * (zero when off).  fdas_plan_stage_times copies the FDAS_NSTAGES
  * totals and the number of searches timed; enabling resets them. */
-#define FDAS_NSTAGES 5
+#define FDAS_NSTAGES 6
 fdas_status fdas_plan_enable_timing(fdas_plan_t *plan, int32_t enable);
 fdas_status fdas_plan_stage_times(const fdas_plan_t *plan, double *ms_out, int64_t *nsearch_out);
 
@@ -192,6 +212,31 @@ fdas_status fdas_search_batch(fdas_plan_t *plan, int32_t n, const float *const *
  * miss appends the new result.  Needs a GPU; allocates temporary plans. */
 fdas_status fdas_autotune(const fdas_bank *bank, int64_t nsamp, const fdas_opts *opts,
                           const char *cache_path, int32_t *seg_out, int32_t *tpb_out, double *ms_out);
+
+/* Fourier-interpolated harmonic sums S(r[i], z[i]) with nharm[i] harmonics
+ * (1..16; NaN otherwise) on the normalised spectrum of the plan's last
+ * fdas_search (the definition is given with refine_levels above), for n
+ * points given in host arrays; results to power_out[n] (host).  For input
+ * kind FDAS_IN_SPECTRUM_C64_NORMALISED the caller's spectrum buffer must
+ * still hold that spectrum.  Synchronous; allocates 28 n bytes of device
+ * memory for the call.  INVAL if no search has completed on the plan or
+ * n < 0; NOMEM if the buffers cannot be allocated. */
+fdas_status fdas_interp_power(fdas_plan_t *plan, int64_t n, const double *r, const double *z, const int32_t *nharm,
+                              double *power_out, void *hip_stream);
+
+/* Refine chosen candidate records, in place, on the normalised spectrum of
+ * the plan's last fdas_search: the pattern search described with
+ * refine_levels above, with `levels` levels (1..20), applied to
+ * cands[0..n) (host records as fdas_search returned them; k, iz and nharm
+ * are read, r, z, power and sigma replaced).  For callers that refine only
+ * the candidates they keep (e.g. the most significant after sifting)
+ * rather than every record of the search.  For input kind
+ * FDAS_IN_SPECTRUM_C64_NORMALISED the caller's spectrum buffer must still
+ * hold that spectrum.  Synchronous; allocates 40 n + 4 bytes of device
+ * memory for the call.  INVAL if no search has completed on the plan, n < 0,
+ * levels out of range or a record's nharm is not 1, 2, 4, 8 or 16; NOMEM if
+ * the buffer cannot be allocated. */
+fdas_status fdas_refine(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t levels, void *hip_stream);
 
 /* Test hook: copy the last search's normalised spectrum (c64[Nb]) and block
  * medians (double[ceil(Nb/W)]) to device buffers; either pointer may be NULL. */

@@ -40,7 +40,8 @@ class _Cand(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("nharm_max", ctypes.c_int32),
                 ("median_window", ctypes.c_int32), ("cand_capacity", ctypes.c_int64),
-                ("templates_per_block", ctypes.c_int32), ("correlator", ctypes.c_int32)]
+                ("templates_per_block", ctypes.c_int32), ("correlator", ctypes.c_int32),
+                ("refine_levels", ctypes.c_int32)]
 
 
 CAND_DTYPE = np.dtype([("k", "<i8"), ("iz", "<i4"), ("nharm", "<i4"), ("r", "<f8"), ("z", "<f8"),
@@ -89,6 +90,8 @@ def load():
         "fdas_search_batch": (_c_i32, [_c_vp, _c_i32, P(_c_vp), P(_c_i64), P(_Cand), P(_c_i64),
                                        P(_c_i64), _c_vp]),
         "fdas_plan_fetch_spectrum": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp]),
+        "fdas_interp_power": (_c_i32, [_c_vp, _c_i64, P(_c_dbl), P(_c_dbl), P(_c_i32), P(_c_dbl), _c_vp]),
+        "fdas_refine": (_c_i32, [_c_vp, _c_vp, _c_i64, _c_i32, _c_vp]),
         "fdas_plan_enable_timing": (_c_i32, [_c_vp, _c_i32]),
         "fdas_plan_stage_times": (_c_i32, [_c_vp, P(_c_dbl), P(_c_i64)]),
         "fdas_plan_search_counts": (_c_i32, [_c_vp, P(_c_i64)]),
@@ -132,7 +135,8 @@ def _stream_handle(stream=None):
 CORRELATORS = {"fft": 0, "bf16": 1, "f16": 2}
 
 
-def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=0, templates_per_block=0, correlator="fft"):
+def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=0, templates_per_block=0, correlator="fft",
+          refine_levels=0):
     o = _Opts()
     load().fdas_default_opts(ctypes.byref(o))
     o.sigma = float(sigma)
@@ -143,6 +147,7 @@ def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=0, template
     if correlator not in CORRELATORS:
         raise ValueError(f"correlator must be one of {sorted(CORRELATORS)}")
     o.correlator = CORRELATORS[correlator]
+    o.refine_levels = int(refine_levels)
     return o
 
 
@@ -305,14 +310,37 @@ class Plan:
             self._h, ctypes.c_void_p(spectrum.data_ptr() if spectrum is not None else 0),
             ctypes.c_void_p(medians.data_ptr() if medians is not None else 0), _stream_handle(stream)))
 
-    STAGES = ("r2c", "unpack_median", "segment_dft", "correlate", "harmonic_sum")
+    def interp_power(self, r, z, nharm, stream=None) -> np.ndarray:
+        """Fourier-interpolated harmonic sums S(r, z) (FP64) with nharm
+        harmonics on the normalised spectrum of the last search."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        nh = np.ascontiguousarray(np.broadcast_to(np.asarray(nharm, dtype=np.int32), r.shape))
+        if z.shape != r.shape:
+            raise ValueError("r and z must have the same shape")
+        out = np.empty(r.shape, dtype=np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(load().fdas_interp_power(
+            self._h, r.size, r.ctypes.data_as(dp), z.ctypes.data_as(dp),
+            nh.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), out.ctypes.data_as(dp), _stream_handle(stream)))
+        return out
+
+    def refine(self, cands: np.ndarray, levels: int = 6, stream=None) -> np.ndarray:
+        """Refined copies of the given candidate records (on the last search's
+        spectrum)."""
+        out = np.ascontiguousarray(cands, dtype=CAND_DTYPE).copy()
+        _check(load().fdas_refine(self._h, ctypes.c_void_p(out.ctypes.data if out.size else 0), out.size,
+                                  int(levels), _stream_handle(stream)))
+        return out
+
+    STAGES = ("r2c", "unpack_median", "segment_dft", "correlate", "harmonic_sum", "refine")
 
     def enable_timing(self, enable: bool = True):
         _check(load().fdas_plan_enable_timing(self._h, int(enable)))
 
     def stage_times(self):
         """(dict stage -> total ms, number of timed searches)."""
-        ms = (ctypes.c_double * 5)()
+        ms = (ctypes.c_double * len(self.STAGES))()
         n = ctypes.c_int64()
         _check(load().fdas_plan_stage_times(self._h, ms, ctypes.byref(n)))
         return dict(zip(self.STAGES, list(ms))), n.value

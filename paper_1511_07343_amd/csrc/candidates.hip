@@ -8,6 +8,7 @@
 #include <cstdint>
 
 #include "../../include/fdas.h"
+#include "device_common.hpp"
 #include "kernels.hpp"
 
 namespace fdas {
@@ -203,60 +204,6 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *__res
         __syncthreads();
         base[t] += o;
     }
-}
-
-// ------------------------------------------------- significance (FP64)
-__device__ double log_gamma_survival_d(int n, double s) {
-    if (s <= 0.0) return 0.0;
-    const double ls = log(s);
-    double mx = -INFINITY, lf = 0.0;
-    for (int i = 0; i < n; ++i) {  // log(i!) accumulated exactly enough for i <= 16
-        if (i > 0) lf += log(double(i));
-        mx = fmax(mx, double(i) * ls - lf);
-    }
-    double acc = 0.0;
-    lf = 0.0;
-    for (int i = 0; i < n; ++i) {
-        if (i > 0) lf += log(double(i));
-        acc += exp(double(i) * ls - lf - mx);
-    }
-    return -s + mx + log(acc);
-}
-
-__device__ double log_normal_tail_d(double sg) {
-    if (sg < 30.0) return log(0.5 * erfc(sg * 0.70710678118654752440));
-    const double s2 = 1.0 / (sg * sg);
-    const double series = 1.0 - s2 + 3.0 * s2 * s2 - 15.0 * s2 * s2 * s2 + 105.0 * s2 * s2 * s2 * s2;
-    return -0.5 * sg * sg - log(sg) - 0.91893853320467274178 + log(series);
-}
-
-// sigma with Phi_c(sigma) = Q(n, power): Newton's method on
-// f(sigma) = log Phi_c(sigma) - log Q, with f' = -phi(sigma) / Phi_c(sigma)
-// (f is decreasing and concave), inside a bracket that falls back to
-// bisection whenever a Newton step leaves it.
-__device__ double significance_d(double power, int n) {
-    const double target = log_gamma_survival_d(n, power);
-    double lo = -40.0, hi = 40.0;
-    if (log_normal_tail_d(lo) < target) return lo;
-    while (log_normal_tail_d(hi) > target && hi < 1e9) hi *= 2.0;
-    // start from the tail asymptote log Phi_c(x) ~ -x^2/2 - log(x sqrt(2 pi))
-    double x = sqrt(fmax(-2.0 * target, 1.0));
-    x = fmin(fmax(x, lo), hi);
-    for (int it = 0; it < 100; ++it) {
-        const double lt = log_normal_tail_d(x);
-        const double f = lt - target;
-        if (f > 0.0) lo = x; else hi = x;
-        const double dlog = -exp(-0.5 * x * x - 0.91893853320467274178 - lt);  // d/dx log Phi_c
-        double nx = x - f / dlog;
-        if (fabs(nx - x) <= 1e-12 * fmax(1.0, fabs(x))) {
-            x = nx;
-            break;
-        }
-        if (!(nx > lo && nx < hi)) nx = 0.5 * (lo + hi);
-        x = nx;
-        if (hi - lo <= 1e-12 * fmax(1.0, fabs(hi))) break;
-    }
-    return x;
 }
 
 __global__ __launch_bounds__(256) void k_cand_finalize(const DevCand *__restrict__ dc,

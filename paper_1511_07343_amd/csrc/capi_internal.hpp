@@ -73,8 +73,8 @@ struct fdas_plan_s {
     bool broken = false;
     // stage timing (fdas_plan_enable_timing)
     bool timing = false;
-    std::array<hipEvent_t, 6> tev{};
-    std::array<double, 5> stage_ms{};
+    std::array<hipEvent_t, FDAS_NSTAGES + 1> tev{};
+    std::array<double, FDAS_NSTAGES> stage_ms{};
     int64_t timed = 0;
     // last search, for the inspection hook
     const float2 *last_X = nullptr;

@@ -59,6 +59,10 @@ fdas_status validate_opts(const fdas_opts &o) {
         set_error("opts.templates_per_block must be in [0, 4096]");
         return FDAS_E_INVAL;
     }
+    if (o.refine_levels < 0 || o.refine_levels > 20) {
+        set_error("opts.refine_levels must be in [0, 20]");
+        return FDAS_E_INVAL;
+    }
     return FDAS_OK;
 }
 
@@ -107,7 +111,7 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
     hipError_t e;
     const float2 *X = nullptr;
     const double *med = nullptr;
-    // event i is recorded before stage i (and event 5 after the last stage)
+    // event i is recorded before stage i (and event FDAS_NSTAGES after the last)
     auto mark = [&](int i) -> hipError_t { return timed ? hipEventRecord(p->tev[size_t(i)], st) : hipSuccess; };
     if ((e = mark(0)) != hipSuccess) return hip_fail(p, e, "timing event");
     if (in_kind == FDAS_IN_SERIES_F32) {
@@ -153,6 +157,13 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
     e = launch_finish_candidates(dcands, dcount, p->cand_cap, ws.sort, p->nz, g.nb, p->zmax, p->dz, ws.final, st);
     if (e != hipSuccess) return hip_fail(p, e, "candidate sort");
     if ((e = mark(5)) != hipSuccess) return hip_fail(p, e, "timing event");
+    if (p->opts.refine_levels > 0) {
+        // four workgroups per compute unit, looping over the records
+        e = launch_refine(X, med, p->W, g.nb, p->h, p->izc, p->dz, p->zmax, p->opts.refine_levels, dcount,
+                          p->cand_cap, ws.final, 4 * p->num_cu, st);
+        if (e != hipSuccess) return hip_fail(p, e, "candidate refinement");
+    }
+    if ((e = mark(6)) != hipSuccess) return hip_fail(p, e, "timing event");
     p->last_X = X;
     p->last_med = med;
     p->last_nb = g.nb;
@@ -161,7 +172,7 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
 
 // Add the stage times of the last timed search (its events have completed).
 fdas_status accumulate_timing(fdas_plan_s *p) {
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < FDAS_NSTAGES; ++i) {
         float ms = 0.f;
         hipError_t e = hipEventElapsedTime(&ms, p->tev[size_t(i)], p->tev[size_t(i) + 1]);
         if (e != hipSuccess) return hip_fail(p, e, "stage timing");
@@ -627,6 +638,87 @@ fdas_status fdas_plan_fetch_spectrum(fdas_plan_t *plan, void *spectrum_dev, doub
     }
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(plan, e, "fetch");
+    return FDAS_OK;
+}
+
+fdas_status fdas_interp_power(fdas_plan_t *plan, int64_t n, const double *r, const double *z, const int32_t *nharm,
+                              double *power_out, void *hip_stream) {
+    if (!plan || !plan->last_X) {
+        set_error("no search has run on this plan");
+        return FDAS_E_INVAL;
+    }
+    if (n < 0 || n > (int64_t(1) << 31) || (n > 0 && (!r || !z || !nharm || !power_out))) {
+        set_error("fdas_interp_power: n out of range or a NULL array");
+        return FDAS_E_INVAL;
+    }
+    if (n == 0) return FDAS_OK;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const size_t nd = size_t(n) * sizeof(double);
+    char *buf = nullptr;
+    hipError_t e = hipMalloc(&buf, 3 * nd + size_t(n) * sizeof(int32_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("fdas_interp_power: device allocation failed");
+        return FDAS_E_NOMEM;
+    }
+    double *dr = reinterpret_cast<double *>(buf);
+    double *dzv = dr + n;
+    double *dout = dzv + n;
+    int32_t *dnh = reinterpret_cast<int32_t *>(dout + n);
+    const int64_t nb = plan->last_nb;
+    if ((e = hipMemcpyAsync(dr, r, nd, hipMemcpyHostToDevice, st)) == hipSuccess &&
+        (e = hipMemcpyAsync(dzv, z, nd, hipMemcpyHostToDevice, st)) == hipSuccess &&
+        (e = hipMemcpyAsync(dnh, nharm, size_t(n) * sizeof(int32_t), hipMemcpyHostToDevice, st)) == hipSuccess &&
+        (e = launch_interp_points(plan->last_X, plan->last_med, plan->W, nb, plan->h, dr, dzv, dnh, n, dout, st)) ==
+            hipSuccess &&
+        (e = hipMemcpyAsync(power_out, dout, nd, hipMemcpyDeviceToHost, st)) == hipSuccess) {
+        e = hipStreamSynchronize(st);
+    }
+    const hipError_t ef = hipFree(buf);
+    if (e != hipSuccess) return hip_fail(plan, e, "interpolated power");
+    if (ef != hipSuccess) return hip_fail(plan, ef, "free");
+    return FDAS_OK;
+}
+
+fdas_status fdas_refine(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t levels, void *hip_stream) {
+    if (!plan || !plan->last_X) {
+        set_error("no search has run on this plan");
+        return FDAS_E_INVAL;
+    }
+    if (n < 0 || n > int64_t(UINT32_MAX) || (n > 0 && !cands) || levels < 1 || levels > 20) {
+        set_error("fdas_refine: n out of range, NULL records or levels not in [1, 20]");
+        return FDAS_E_INVAL;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t m = cands[i].nharm;
+        if (m != 1 && m != 2 && m != 4 && m != 8 && m != 16) {
+            set_error("fdas_refine: a record's nharm is not 1, 2, 4, 8 or 16");
+            return FDAS_E_INVAL;
+        }
+    }
+    if (n == 0) return FDAS_OK;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const size_t bytes = size_t(n) * sizeof(fdas_cand);
+    char *buf = nullptr;
+    hipError_t e = hipMalloc(&buf, bytes + sizeof(uint32_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("fdas_refine: device allocation failed");
+        return FDAS_E_NOMEM;
+    }
+    fdas_cand *dc = reinterpret_cast<fdas_cand *>(buf);
+    uint32_t *dn = reinterpret_cast<uint32_t *>(buf + bytes);
+    const uint32_t nn = uint32_t(n);
+    if ((e = hipMemcpyAsync(dc, cands, bytes, hipMemcpyHostToDevice, st)) == hipSuccess &&
+        (e = hipMemcpyAsync(dn, &nn, sizeof(nn), hipMemcpyHostToDevice, st)) == hipSuccess &&
+        (e = launch_refine(plan->last_X, plan->last_med, plan->W, plan->last_nb, plan->h, plan->izc, plan->dz,
+                           plan->zmax, levels, dn, nn, dc, 4 * plan->num_cu, st)) == hipSuccess &&
+        (e = hipMemcpyAsync(cands, dc, bytes, hipMemcpyDeviceToHost, st)) == hipSuccess) {
+        e = hipStreamSynchronize(st);
+    }
+    const hipError_t ef = hipFree(buf);
+    if (e != hipSuccess) return hip_fail(plan, e, "refine");
+    if (ef != hipSuccess) return hip_fail(plan, ef, "free");
     return FDAS_OK;
 }
 

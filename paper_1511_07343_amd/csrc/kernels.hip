@@ -248,21 +248,27 @@ __global__ __launch_bounds__(256) void k_normalise(const float2 *__restrict__ X,
 }
 
 // ----------------------------------------------- fused correlation kernel
-// Work item u = (template block tb, segment s), tb-major.  Workgroup i runs
-// item u = (i mod 8) * per + i div 8, so each XCD walks a contiguous range of
-// template blocks over all segments and keeps its templates in its own L2.
+// Work item u enumerates (group of grp template blocks, segment s, block in
+// the group), group-major.  Workgroup i runs item u = (i mod 8) * per + i div 8,
+// so each XCD walks a contiguous range of items: when the template blocks split
+// evenly over the 8 XCDs, one group of blocks over all segments, with the
+// group's templates kept in its own L2 and each segment spectrum read by the
+// group's blocks while still resident.
 template <int LOG2S>
 __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
     const float2 *__restrict__ segspec, const float2 *__restrict__ bank, int nz, int tpb, int64_t nb,
-    int h, int64_t nseg, int64_t total, int64_t per, float *__restrict__ plane, uint8_t *__restrict__ codes,
-    float code_inv) {
+    int h, int64_t nseg, int64_t total, int64_t per, int grp, float *__restrict__ plane,
+    uint8_t *__restrict__ codes, float code_inv) {
     using Sh = FftShape<LOG2S, corr_threads(LOG2S)>;
     __shared__ float2 lds[Sh::LDS_FLOAT2];
     const int t = threadIdx.x;
     const int64_t u = int64_t(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
     if (u >= total) return;
-    const int64_t tb = u / nseg;
-    const int64_t s = u - tb * nseg;
+    const int64_t gsz = int64_t(grp) * nseg;
+    const int64_t gi = u / gsz;
+    const int64_t gr = u - gi * gsz;
+    const int64_t s = gr / grp;
+    const int64_t tb = gi * grp + (gr - s * grp);
     const int64_t L = seg_valid(Sh::S, h);
     const int iz0 = int(tb) * tpb;
     const int iz1 = min(nz, iz0 + tpb);
@@ -840,9 +846,11 @@ hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, i
     const int64_t per = (total + kXcds - 1) / kXcds;
     const int64_t grid = per * kXcds;
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
+    // template blocks per group: the blocks of one XCD when they split evenly
+    const int grp = (nzb % kXcds == 0) ? int(nzb / kXcds) : 1;
 #define CALL(L)                                                                                       \
     hipLaunchKernelGGL((k_correlate<L>), dim3(unsigned(grid)), dim3(corr_threads(L)), 0, st, segspec, bank, \
-                       nz, tpb, nb, h, nseg, total, per, plane, codes, code_inv);
+                       nz, tpb, nb, h, nseg, total, per, grp, plane, codes, code_inv);
     FDAS_SWITCH_LOG2(log2s, CALL)
 #undef CALL
     return hipGetLastError();

@@ -100,4 +100,20 @@ size_t cand_sort_scratch_bytes(uint32_t cap);
 hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch, int nz,
                                     int64_t nb, double zmax, double dz, fdas_cand *out, hipStream_t st);
 
+// Candidate refinement (Fourier interpolation off the grid): for each of the
+// first min(*count, cap) public records, a pattern search over the
+// fundamental (r, z) for the largest S(r, z) = sum_{j=1}^{nh} P(j r, j z),
+// P the correlation power with the response evaluated at the exact offset
+// and drift; levels step halvings from half a grid cell.  r, z, power and
+// sigma of the records are replaced by those of the final point.  The
+// spectrum is X scaled by sqrt(ln2 / m(k)) (X itself when med is NULL), as in
+// the search.  A persistent grid of `workgroups` workgroups.
+hipError_t launch_refine(const float2 *X, const double *med, int W, int64_t nb, int h, int izc, double dz,
+                         double zmax, int levels, const uint32_t *count, uint32_t cap, fdas_cand *cands,
+                         int workgroups, hipStream_t st);
+// out[i] = S(r[i], z[i]) with nh[i] harmonics (NaN when nh[i] is not in 1..16),
+// device arrays of n entries.
+hipError_t launch_interp_points(const float2 *X, const double *med, int W, int64_t nb, int h, const double *r,
+                                const double *z, const int32_t *nh, int64_t n, double *out, hipStream_t st);
+
 }  // namespace fdas
