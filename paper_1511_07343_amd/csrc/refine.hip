@@ -5,6 +5,7 @@
 // integer offsets of the template bank.  Everything is FP64 except the
 // spectrum, which is read in FP32 as the search holds it.
 #include "device_common.hpp"
+#include "fresnel_coeffs.hpp"
 #include "kernels.hpp"
 
 #include <cmath>
@@ -48,61 +49,85 @@ __device__ c64 cis_pi(double x) {
     return {c, s};
 }
 
-// Fresnel integral F(x) = C(x) + i S(x), C(x) = int_0^x cos(pi t^2 / 2) dt,
-// for 0 <= x < 1.5 from its power series
-//   F(x) = sum_m (i pi x^2 / 2)^m / m! * x / (2m + 1).
-__device__ c64 fresnel_series(double x) {
-    const c64 w = {0.0, 0.5 * kPiD * x * x};
-    c64 term = {1.0, 0.0};
-    c64 sum = {x, 0.0};
-    for (int m = 1; m < 80; ++m) {
-        term = cscale(cmul(term, w), 1.0 / double(m));
-        const c64 add = cscale(term, x / double(2 * m + 1));
-        sum = cadd(sum, add);
-        if (cnorm2(add) < 1e-36 * cnorm2(sum)) break;
+// Fresnel integrals F(x) = C(x) + i S(x), C(x) = int_0^x cos(pi t^2 / 2) dt,
+// from the polynomial data of fresnel_coeffs.hpp (written by
+// gen_fresnel_coeffs.py): the power series for |x| < 1, and for x >= 1 the
+// auxiliary functions f, g of F(x) = (1 + i)/2 - (g + i f) exp(i pi x^2 / 2)
+// as Chebyshev expansions in u = 1 / x^2 of pi x f and pi^2 x^3 g.  No loop
+// with a data-dependent trip count, no division inside.
+template <int N>
+__device__ __forceinline__ double clenshaw(const double (&c)[N], double t) {
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int j = N - 1; j >= 1; --j) {
+        const double b0 = fma(2.0 * t, b1, c[j] - b2);
+        b2 = b1;
+        b1 = b0;
     }
-    return sum;
+    return fma(t, b1, c[0] - b2);
 }
 
-// Auxiliary G(x) = g(x) + i f(x), x >= 1.5, with F(x) = (1 + i)/2 - G(x) exp(i pi x^2 / 2).
-// F(x) = (1 + i)/2 erf(zeta) with zeta = (sqrt(pi)/2)(1 - i) x, and
-// erfc(zeta) = exp(-zeta^2) K(zeta) / sqrt(pi), K(zeta) = 2 zeta / t with the
-// even part of Laplace's continued fraction of erfc,
-//   t = b0 - a1 / (b1 - a2 / (b2 - ...)),  b_n = 2 zeta^2 + 1 + 4n,  a_n = (2n - 1)(2n),
-// give G = (1 + i) K / (2 sqrt(pi)) = x / t.  Here 2 zeta^2 = -i pi x^2, and t
-// is evaluated backwards from depth N = ceil(110 / x^2) + 6, which is past the
-// point where the forward approximants agree to 1e-16 for every x >= 1.5
-// (55 terms at 1.5, 8 at 10); each step costs one real division.
-__device__ c64 fresnel_aux(double x) {
-    const double w = kPiD * x * x;
-    const int N = int(ceil(110.0 / (x * x))) + 6;
-    c64 t = {1.0 + 4.0 * double(N), -w};
-    for (int n = N; n >= 1; --n) {
-        const double s = double(2 * n - 1) * double(2 * n) / cnorm2(t);  // a_n / t = s conj(t)
-        t = {1.0 + 4.0 * double(n - 1) - s * t.re, -w + s * t.im};
+// F(x) for |x| < 1: C = x sum c_n x^4n, S = x^3 sum s_n x^4n (Horner).
+__device__ __forceinline__ c64 fresnel_small(double x) {
+    using namespace fresnel_data;
+    const double x2 = x * x, t = x2 * x2;
+    double c = kSeriesC[kSeriesTerms - 1], sn = kSeriesS[kSeriesTerms - 1];
+#pragma unroll
+    for (int n = kSeriesTerms - 2; n >= 0; --n) {
+        c = fma(c, t, kSeriesC[n]);
+        sn = fma(sn, t, kSeriesS[n]);
     }
-    return cscale(cinv(t), x);
+    return {x * c, x * x2 * sn};
 }
 
-__device__ c64 fresnel(double x) {
+// G(x) = g(x) + i f(x) for x >= 1.  The expansion of each u interval is run
+// under a wave-uniform test, so that its coefficients are read with uniform
+// (scalar) loads; lanes outside the interval keep their values.
+__device__ __forceinline__ c64 fresnel_aux(double x) {
+    using namespace fresnel_data;
+    const double u = 1.0 / (x * x);
+    const int iv = u < kUHi[0] ? 0 : u < kUHi[1] ? 1 : u < kUHi[2] ? 2 : 3;
+    double pf = 0.0, pg = 0.0;
+    auto fit = [&](const auto &cf, const auto &cg, int i) {
+        if (__any(iv == i) && iv == i) {
+            const double t = (2.0 * u - (kUHi[i] + kULo[i])) / (kUHi[i] - kULo[i]);
+            pf = clenshaw(cf, t);
+            pg = clenshaw(cg, t);
+        }
+    };
+    fit(kPhiF0, kPhiG0, 0);
+    fit(kPhiF1, kPhiG1, 1);
+    fit(kPhiF2, kPhiG2, 2);
+    fit(kPhiF3, kPhiG3, 3);
+    const double ipx = 1.0 / (kPiD * x);  // f = phi_f / (pi x), g = phi_g / (pi^2 x^3)
+    return {pg * u * ipx * (1.0 / kPiD), pf * ipx};
+}
+
+// H(x) = F(x) exp(-i pi x^2 / 2); H(-x) = -H(x).
+__device__ c64 fresnel_h(double x) {
     const double ax = fabs(x);
-    c64 r;
-    if (ax < 1.5) {
-        r = fresnel_series(ax);
+    const c64 rot = cis_pi(-0.5 * ax * ax);
+    c64 h;
+    if (ax < 1.0) {
+        h = cmul(fresnel_small(ax), rot);
     } else {
-        r = csub({0.5, 0.5}, cmul(fresnel_aux(ax), cis_pi(0.5 * ax * ax)));
+        const c64 g = fresnel_aux(ax);
+        h = {0.5 * (rot.re - rot.im) - g.re, 0.5 * (rot.re + rot.im) - g.im};  // (1 + i)/2 rot - G
     }
-    return x < 0.0 ? c64{-r.re, -r.im} : r;
+    return x < 0.0 ? c64{-h.re, -h.im} : h;
 }
 
 // A(q, z) = int_0^1 exp(2 pi i [(q - z/2) u + z u^2 / 2]) du: the Fourier
 // response at offset q bins of a unit tone whose frequency drifts by z bins
-// over the observation (Sec. 2).  z = 0: exp(i pi q) sin(pi q) / (pi q).
-// z > 0: with p = q - z/2, Y = p sqrt(2/z), Z = Y + sqrt(2z),
-//   A = exp(-i pi p^2 / z) (F(Z) - F(Y)) / sqrt(2z);
-// when Y and Z lie on the same tail the (1 + i)/2 terms cancel exactly and
-// the auxiliary functions are used directly.  z < 0: conj(A(-q, -z)).
-__device__ c64 accel_response(double q, double z) {
+// over the observation (Sec. 2); e2q = exp(2 pi i q) is passed in (it is the
+// same for every integer shift of q).  z = 0: exp(i pi q) sin(pi q) / (pi q).
+// z > 0: with p = q - z/2, Y = p sqrt(2/z), Z = Y + sqrt(2z) (so that
+// pi (Z^2 - Y^2) / 2 = 2 pi q),
+//   A = exp(-i pi Y^2 / 2) (F(Z) - F(Y)) / sqrt(2z) = (e2q H(Z) - H(Y)) / sqrt(2z);
+// when |Y|, |Z| >= 1 on one side the (1 + i)/2 parts of H cancel exactly and
+// A = (G(Y) - e2q G(Z)) / sqrt(2z) (both positive) or
+// (e2q G(-Z) - G(-Y)) / sqrt(2z) (both negative).  z < 0: conj(A(-q, -z)).
+__device__ c64 accel_response(double q, double z, c64 e2q) {
     if (z == 0.0) {
         if (q == rint(q)) return q == 0.0 ? c64{1.0, 0.0} : c64{0.0, 0.0};
         return cscale(cis_pi(q), sinpi(q) / (kPiD * q));
@@ -112,20 +137,21 @@ __device__ c64 accel_response(double q, double z) {
         neg = true;
         q = -q;
         z = -z;
+        e2q.im = -e2q.im;
     }
     const double p = q - 0.5 * z;
     const double s = sqrt(2.0 / z);
     const double Y = p * s, Zv = (p + z) * s;
     const double pre = 1.0 / sqrt(2.0 * z);
     c64 a;
-    if (Y >= 1.5) {
-        // exp(i pi (Z^2 - Y^2) / 2) = exp(2 pi i q)
-        a = cscale(csub(fresnel_aux(Y), cmul(fresnel_aux(Zv), cis_pi(2.0 * q))), pre);
-    } else if (Zv <= -1.5) {
-        a = cscale(csub(cmul(fresnel_aux(-Zv), cis_pi(2.0 * q)), fresnel_aux(-Y)), pre);
+    if (Y >= 1.0) {
+        a = csub(fresnel_aux(Y), cmul(e2q, fresnel_aux(Zv)));
+    } else if (Zv <= -1.0) {
+        a = csub(cmul(e2q, fresnel_aux(-Zv)), fresnel_aux(-Y));
     } else {
-        a = cscale(cmul(cis_pi(-(p * p / z)), csub(fresnel(Zv), fresnel(Y))), pre);
+        a = csub(cmul(e2q, fresnel_h(Zv)), fresnel_h(Y));
     }
+    a = cscale(a, pre);
     return neg ? c64{a.re, -a.im} : a;
 }
 
@@ -159,9 +185,10 @@ __device__ double wave_power(const Spectrum &sp, int h, double r, double z, int 
     const double klo = ceil(r - double(h));
     const int ntap = int(floor(r + double(h)) - klo) + 1;  // 2h or 2h + 1
     double nre = 0.0, nim = 0.0, den = 0.0;
+    const c64 e2q = cis_pi(2.0 * r);  // exp(2 pi i (r - k)) for every integer k
     for (int t = lane; t < ntap; t += 64) {
         const double kk = klo + double(t);
-        const c64 a = accel_response(r - kk, z);
+        const c64 a = accel_response(r - kk, z, e2q);
         den += cnorm2(a);
         const int64_t k = int64_t(kk);
         if (k >= 0 && k < sp.nb) {
