@@ -77,6 +77,7 @@ extern "C" fdas_status fdas_autotune(const fdas_bank *bank, int64_t nsamp, const
     float *dx = nullptr;
     hipError_t e = hipMalloc(reinterpret_cast<void **>(&dx), size_t(nsamp) * 4);
     if (e != hipSuccess) {
+        (void)hipGetLastError();
         set_error("autotune: device allocation failed");
         return FDAS_E_NOMEM;
     }

@@ -20,6 +20,7 @@ static fdas_status ensure_batch_resources(fdas_plan_s *p) {
         if (!p->ws[i].series) {
             hipError_t e = hipMalloc(reinterpret_cast<void **>(&p->ws[i].series), size_t(p->nsamp) * 4);
             if (e != hipSuccess) {
+                (void)hipGetLastError();
                 set_error("hipMalloc batch input buffer");
                 return FDAS_E_NOMEM;
             }

@@ -230,6 +230,7 @@ fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp) {
 #define FDAS_ALLOC(ptr, bytes)                                                  \
     e = hipMalloc(reinterpret_cast<void **>(&(ptr)), size_t(bytes));            \
     if (e != hipSuccess) {                                                      \
+        (void)hipGetLastError(); /* a failed allocation must not fail later launches */ \
         free_workspace(ws);                                                     \
         set_error(std::string("hipMalloc ") + #ptr + ": " + hipGetErrorString(e)); \
         return FDAS_E_NOMEM;                                                    \
@@ -250,6 +251,7 @@ fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp) {
 #undef FDAS_ALLOC
     e = hipHostMalloc(reinterpret_cast<void **>(&ws.h_count), 64, hipHostMallocDefault);
     if (e != hipSuccess) {
+        (void)hipGetLastError();
         free_workspace(ws);
         set_error("hipHostMalloc counter");
         return FDAS_E_NOMEM;
@@ -360,6 +362,7 @@ fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, 
         e = hipMalloc(&p->d_gemm, gm.size());
         if (e == hipSuccess) e = hipMemcpy(p->d_gemm, gm.data(), gm.size(), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
+            (void)hipGetLastError();
             if (p->d_gemm) (void)hipFree(p->d_gemm);
             delete p;
             set_error(std::string("template matrix: ") + hipGetErrorString(e));
@@ -384,6 +387,7 @@ fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, 
     }
     e = hipMalloc(reinterpret_cast<void **>(&p->d_bank), host.size() * sizeof(float2));
     if (e != hipSuccess) {
+        (void)hipGetLastError();
         delete p;
         set_error(std::string("hipMalloc bank: ") + hipGetErrorString(e));
         return FDAS_E_NOMEM;

@@ -172,6 +172,7 @@ static void scheduler(fdas_server_s *sv) {
                 hipError_t e = hipSuccess;
                 if (s == FDAS_OK) e = hipMalloc(reinterpret_cast<void **>(&buf->series), size_t(req.nsamp) * 4);
                 if (s != FDAS_OK || e != hipSuccess) {
+                    (void)hipGetLastError();
                     free_buffers(buf);
                     buf = nullptr;
                     // fail this request rather than block the queue
@@ -318,6 +319,7 @@ fdas_status fdas_submit(fdas_server *sv, const float *series_host, int64_t nsamp
     }
     if (!host) {
         if (hipHostMalloc(reinterpret_cast<void **>(&host), size_t(nsamp) * 4, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
             set_error("pinned host allocation failed");
             return FDAS_E_NOMEM;
         }

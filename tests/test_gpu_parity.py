@@ -410,3 +410,11 @@ def test_device_memory_exhaustion_is_nomem(gpu_lib):
         gpu_lib.Plan(bank, 1 << 26, 8192)  # plane alone: 4801 x 2^25 x 4 B = 644 GB
     assert e.value.status == -2
     bank.close()
+    # the failed allocation leaves no error behind for the next plan's launches
+    t = synth.make_series(1 << 14, seed=3)
+    bank = gpu_lib.make_templates(10.0, 2.0)
+    plan = gpu_lib.Plan(bank, 1 << 14, 256, nharm_max=1)
+    cands, n = plan.search(_dev(t.x))
+    assert n == len(cands)
+    plan.close()
+    bank.close()
