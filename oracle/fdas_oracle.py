@@ -48,6 +48,8 @@ __all__ = [
     "halfwidth",
     "z_values",
     "template_taps",
+    "template_taps_half",
+    "interbin_plane",
     "correlate",
     "correlate_cells",
     "harmonic_list",
@@ -204,6 +206,31 @@ def template_taps(zmax: float, dz: float, h: int | None = None):
         a = template_response(q, float(z))
         taps[i] = np.conj(a) / np.sqrt(np.sum(np.abs(a) ** 2))
     return taps, zs, h
+
+
+def template_taps_half(zmax: float, dz: float, h: int | None = None):
+    """Half-bin taps T'[iz, q + h] = conj(A(q + 1/2, z_iz)) / norm for
+    q = -h .. h-1 and 0 at q = h: the template of the correlation at the
+    point halfway between bins k and k + 1 (the offsets r - k' of the bins k'
+    within h of r = k + 1/2), normalised over those 2h taps (reading; an
+    extension past the paper's method).  Returns (taps, zs, h)."""
+    if h is None:
+        h = halfwidth(zmax)
+    zs = z_values(zmax, dz)
+    q = np.arange(-h, h, dtype=np.float64) + 0.5
+    taps = np.zeros((zs.shape[0], 2 * h + 1), dtype=np.complex128)
+    for i, z in enumerate(zs):
+        a = template_response(q, float(z))
+        taps[i, :2 * h] = np.conj(a) / np.sqrt(np.sum(np.abs(a) ** 2))
+    return taps, zs, h
+
+
+def interbin_plane(P: np.ndarray, P_half: np.ndarray) -> np.ndarray:
+    """Half-bin plane: column 2k = P[:, k] (bin k), 2k + 1 = P_half[:, k] (k + 1/2)."""
+    out = np.empty((P.shape[0], 2 * P.shape[1]), dtype=np.float64)
+    out[:, 0::2] = P
+    out[:, 1::2] = P_half
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -422,11 +449,13 @@ class SearchResult:
 
 def search(x=None, *, spectrum=None, normalised: bool = False, zmax: float, dz: float,
            sigma: float = 6.0, nharm_max: int = 16, W: int = 1024,
-           keep_sums: bool = False) -> SearchResult:
+           keep_sums: bool = False, interbin: bool = False) -> SearchResult:
     """The whole hot path on one series (or spectrum), every step in FP64.
 
     Candidates are reported per harmonic count, sorted by (nharm, k, iz); r and
-    z describe the fundamental: r = k / nharm, z = z(iz) / nharm.
+    z describe the fundamental: r = k / nharm, z = z(iz) / nharm.  With
+    interbin the plane has 2 nb columns (``interbin_plane``), k counts half
+    bins and r = k / (2 nharm).
     """
     if x is not None:
         X = real_spectrum(x)
@@ -435,6 +464,10 @@ def search(x=None, *, spectrum=None, normalised: bool = False, zmax: float, dz: 
     Xhat = X if normalised else normalise(X, W)
     taps, zs, h = template_taps(zmax, dz)
     P = correlate(Xhat, taps)
+    cpb = 1
+    if interbin:
+        P = interbin_plane(P, correlate(Xhat, template_taps_half(zmax, dz, h)[0]))
+        cpb = 2
     izc = int(round(zmax / dz))
     nhs = harmonic_list(nharm_max)
     thr = thresholds(sigma, nhs)
@@ -446,7 +479,7 @@ def search(x=None, *, spectrum=None, normalised: bool = False, zmax: float, dz: 
             sums[nh] = S
         for iz, k in find_peaks(S, thr[nh]):
             s = float(S[iz, k])
-            cands.append(Candidate(k=int(k), iz=int(iz), nharm=nh, r=k / nh, z=float(zs[iz]) / nh,
+            cands.append(Candidate(k=int(k), iz=int(iz), nharm=nh, r=k / (nh * cpb), z=float(zs[iz]) / nh,
                                    power=s, sigma=sigma_of(s, nh)))
     return SearchResult(plane=P, candidates=cands, thresholds=thr, spectrum=Xhat, zs=zs, h=h,
                         sums=sums)
@@ -481,9 +514,10 @@ def interp_sum(Xhat: np.ndarray, r: float, z: float, nh: int, h: int) -> float:
     return float(sum(interp_power(Xhat, j * r, j * z, h) for j in range(1, nh + 1)))
 
 
-def refine_start(k: int, iz: int, nh: int, dz: float, izc: int):
-    """Fundamental of a candidate cell: r = k / nh, z = ((iz - izc) dz) / nh."""
-    return k / nh, (float(iz - izc) * dz) / nh
+def refine_start(k: int, iz: int, nh: int, dz: float, izc: int, cpb: int = 1):
+    """Fundamental of a candidate cell: r = k / (nh cpb), z = ((iz - izc) dz) / nh
+    (cpb = 2 plane columns per bin on a half-bin plane)."""
+    return k / (nh * cpb), (float(iz - izc) * dz) / nh
 
 
 def _refine_level(Xhat, r, z, level, nh, dz, zmax, h):
@@ -507,7 +541,7 @@ def _refine_level(Xhat, r, z, level, nh, dz, zmax, h):
 
 
 def refine(Xhat: np.ndarray, k: int, iz: int, nh: int, *, zmax: float, dz: float, h: int,
-           levels: int):
+           levels: int, cpb: int = 1):
     """Pattern search for the largest S(r, z) around a candidate (reading).
 
     Start at the candidate's fundamental; at each level l = 1 .. levels look
@@ -519,7 +553,7 @@ def refine(Xhat: np.ndarray, k: int, iz: int, nh: int, *, zmax: float, dz: float
     (r, z, S, sigma) of the final point.
     """
     izc = int(round(zmax / dz))
-    r, z = refine_start(k, iz, nh, dz, izc)
+    r, z = refine_start(k, iz, nh, dz, izc, cpb)
     best = interp_sum(Xhat, r, z, nh, h)
     for level in range(1, levels + 1):
         br, bz = r, z
@@ -531,13 +565,13 @@ def refine(Xhat: np.ndarray, k: int, iz: int, nh: int, *, zmax: float, dz: float
 
 
 def refine_endpoints(Xhat: np.ndarray, k: int, iz: int, nh: int, *, zmax: float, dz: float, h: int,
-                     levels: int, tol, max_paths: int = 1024):
+                     levels: int, tol, max_paths: int = 1024, cpb: int = 1):
     """Every end point the search of ``refine`` can reach when values within
     tol(S) of a level's best count as ties (either may win in a different
     rounding): a dict {(r, z): S}.  Used to check a result computed in lower
     precision, where near-equal neighbours may be ordered differently."""
     izc = int(round(zmax / dz))
-    r0, z0 = refine_start(k, iz, nh, dz, izc)
+    r0, z0 = refine_start(k, iz, nh, dz, izc, cpb)
     paths = [(r0, z0, interp_sum(Xhat, r0, z0, nh, h))]
     for level in range(1, levels + 1):
         nxt = {}
