@@ -25,6 +25,7 @@ Prints one JSON line: the plain per-trial rate as ``value``, then
              significant records of the trial refined by fdas_refine, and
              the small configuration with every candidate refined;
   template_sweep  the plain rate at 51, 101, 201 and 401 templates;
+  interbin   the plain rate with the half-bin plane (2 Nb columns);
   precision  16 trials of 2^22 samples, 801 templates (z in [-400, 400],
              step 1): FP32 FFT correlation against the BF16 and FP16
              matrix-core correlators, with power error and candidate
@@ -319,6 +320,32 @@ def bench_refine(fdas, plan, x, h: int, top: int = 256, levels: int = 6, reps: i
     return out
 
 
+def bench_interbin(fdas, bank, xs, pinned, steps: int = 8):
+    """The SKA-shaped trial with the half-bin plane (2 Nb columns: templates
+    at integer and half-bin offsets, harmonic sums on half bins)."""
+    import numpy as np
+    import torch
+    plan = fdas.Plan(bank, N, SEG, nharm_max=NHARM, sigma=SIGMA, interbin=True)
+    for i in range(2):
+        plan.search(xs[i % len(xs)], out=pinned)
+    torch.cuda.synchronize()
+    plan.enable_timing(True)
+    counts = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        _, n = plan.search(xs[i % len(xs)], out=pinned)
+        counts.append(n)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st, nt = plan.stage_times()
+    out = {"value": round(1.0 / dt, 3), "unit": "DM trials/s", "steps": steps, "ms_per_step": round(1e3 * dt, 4),
+           "plane_columns": plan.plane_columns, "device_bytes": plan.device_bytes,
+           "correlate_ms": round(st["correlate"] / nt, 4), "harmonic_sum_ms": round(st["harmonic_sum"] / nt, 4),
+           "candidates_per_trial": [int(c) for c in counts[:len(xs)]]}
+    plan.close()
+    return out
+
+
 C5_ZMAX, C5_DZ, C5_N = 400.0, 1.0, 1 << 22
 
 
@@ -539,6 +566,10 @@ def main():
     if extra and args.sweep:
         log("template-count sweep")
         out["template_sweep"] = bench_template_sweep(fdas, xs, pinned)
+
+    if extra:
+        log("half-bin plane")
+        out["interbin"] = bench_interbin(fdas, bank, xs, pinned)
 
     if batch_host:
         bxs = [torch.from_numpy(x).to(dev) for x in batch_host]

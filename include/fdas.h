@@ -24,7 +24,9 @@
  *   - Series length N is a power of two in [2^10, 2^26]; the spectrum has
  *     Nb = N/2 bins, bin 0 (DC) is zeroed and the Nyquist bin dropped.
  *   - The f-fdot plane is float32[nz][Nb], template-major (row iz holds all
- *     Nb frequency bins of template iz, contiguous in k).
+ *     Nb frequency bins of template iz, contiguous in k); with
+ *     fdas_opts.interbin it is float32[nz][2 Nb], column 2k holding bin k and
+ *     column 2k + 1 the point k + 1/2 between bins k and k + 1.
  */
 #ifndef FDAS_H
 #define FDAS_H
@@ -52,7 +54,8 @@ typedef struct fdas_server_s fdas_server;
 
 /* One candidate: a thresholded local maximum of an nharm-harmonic sum whose
  * top harmonic sits at plane cell (iz, k).  r and z describe the fundamental:
- * r = k / nharm bins, z = z(iz) / nharm bins with z(iz) = -zmax + iz * dz.
+ * r = k / nharm bins, z = z(iz) / nharm bins with z(iz) = -zmax + iz * dz
+ * (with fdas_opts.interbin, k counts half bins and r = k / (2 nharm)).
  * power is the harmonic sum; sigma its Gaussian-equivalent single-trial
  * significance (FP64 on the host). 40 bytes. */
 typedef struct fdas_cand {
@@ -81,7 +84,18 @@ typedef struct fdas_opts {
     int32_t templates_per_block; /* templates per correlation workgroup, 0 = automatic       */
     int32_t correlator;          /* FDAS_CORR_FFT_F32 (default) or a matrix form, see below   */
     int32_t refine_levels;       /* candidate refinement levels, 0 = off (default), <= 20     */
+    int32_t interbin;            /* 1 = half-bin plane (2 Nb columns), 0 = off (default)      */
 } fdas_opts;
+
+/* Half-bin plane (interbin = 1), an extension past the paper's method: a
+ * second template bank at offsets q + 1/2, T'_z[q] = conj(A(q + 1/2, z)) /
+ * norm for q = -h .. h-1 (the 2h offsets within h of the half-bin point),
+ * gives P(k + 1/2, z), interleaved with P(k, z) into a plane of 2 Nb columns
+ * (the interpolated power of the refinement note below at r = k/2).  The
+ * harmonic sums, thresholds and peaks then run on that plane with k in half
+ * bins, so a tone between two bins loses at most sinc^2(1/4) = 0.81 of its
+ * power to scalloping instead of sinc^2(1/2) = 0.41.  Twice the correlation
+ * work and plane memory.  FFT correlator only (INVAL with a matrix one). */
 
 /* Candidate refinement (refine_levels > 0), an extension past the paper's
  * method: Fourier interpolation of the correlation at fractional frequency
@@ -91,7 +105,8 @@ typedef struct fdas_opts {
  * (Xhat zero outside [0, Nb)); at integer r and a bank z it is the plane
  * cell.  S(r, z) = sum_{j=1}^{nharm} P(j r, j z) sums the harmonics at their
  * exact positions.  Each candidate's fundamental then moves by a pattern
- * search: from r = k / nharm, z = ((iz - izc) dz) / nharm (izc = zmax / dz),
+ * search: from r = k / nharm (k / (2 nharm) with interbin),
+ * z = ((iz - izc) dz) / nharm (izc = zmax / dz),
  * level l = 1 .. refine_levels looks at the 8 neighbours at steps
  * (2^-l / nharm, dz 2^-l / nharm), z offset major then r offset, each -1, 0,
  * +1, and moves to the first that beats every earlier value of the level,
@@ -158,8 +173,9 @@ void fdas_plan_destroy(fdas_plan_t *plan);
  * and peaks):
  *   in_kind/in_dev  device input: float32[nsamp] series, or c64[Nb] spectrum
  *                   (caller-owned, read-only).
- *   plane_dev       NULL, or device float32[nz][Nb] that receives the plane
- *                   (16-byte aligned, else INVAL).
+ *   plane_dev       NULL, or device float32[nz][Nb] (float32[nz][2 Nb] with
+ *                   interbin) that receives the plane (16-byte aligned, else
+ *                   INVAL).
  *   cands_host      host array of cap entries; receives candidates sorted by
  *                   (nharm, k, iz).  May be NULL when cap is 0.
  *   ncands          receives the number of candidates found.

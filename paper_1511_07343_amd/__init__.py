@@ -41,7 +41,7 @@ class _Opts(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("nharm_max", ctypes.c_int32),
                 ("median_window", ctypes.c_int32), ("cand_capacity", ctypes.c_int64),
                 ("templates_per_block", ctypes.c_int32), ("correlator", ctypes.c_int32),
-                ("refine_levels", ctypes.c_int32)]
+                ("refine_levels", ctypes.c_int32), ("interbin", ctypes.c_int32)]
 
 
 CAND_DTYPE = np.dtype([("k", "<i8"), ("iz", "<i4"), ("nharm", "<i4"), ("r", "<f8"), ("z", "<f8"),
@@ -136,7 +136,7 @@ CORRELATORS = {"fft": 0, "bf16": 1, "f16": 2}
 
 
 def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=0, templates_per_block=0, correlator="fft",
-          refine_levels=0):
+          refine_levels=0, interbin=False):
     o = _Opts()
     load().fdas_default_opts(ctypes.byref(o))
     o.sigma = float(sigma)
@@ -148,6 +148,7 @@ def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=0, template
         raise ValueError(f"correlator must be one of {sorted(CORRELATORS)}")
     o.correlator = CORRELATORS[correlator]
     o.refine_levels = int(refine_levels)
+    o.interbin = int(bool(interbin))
     return o
 
 
@@ -262,6 +263,11 @@ class Plan:
         return load().fdas_plan_nbins(self._h)
 
     @property
+    def plane_columns(self) -> int:
+        """Columns of the plane: nbins, or 2 nbins for a half-bin plane."""
+        return self.nbins * (2 if self.opts.interbin else 1)
+
+    @property
     def device_bytes(self) -> int:
         return load().fdas_plan_device_bytes(self._h)
 
@@ -275,6 +281,8 @@ class Plan:
         buf = out if out is not None else self._buf.get(max(cap, 1))
         if out is not None:
             cap = min(cap, out.shape[0])
+        if plane is not None and plane.numel() * plane.element_size() < 4 * self.bank.nz * self.plane_columns:
+            raise ValueError(f"plane must hold float32[{self.bank.nz}][{self.plane_columns}]")
         n = ctypes.c_int64()
         st = load().fdas_search(self._h, kind, ctypes.c_void_p(inp.data_ptr()),
                                 ctypes.c_void_p(plane.data_ptr() if plane is not None else 0),

@@ -50,7 +50,7 @@ static fdas_status slot_graph(fdas_plan_s *p, int i, int64_t nsamp, hipGraphExec
     hipStream_t st = p->aux[size_t(i)];
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(p, e, "begin capture");
-    const Geometry g = make_geometry(nsamp, p->S, p->h, p->W);
+    const Geometry g = make_geometry(nsamp, p->S, p->h, p->W, cols_per_bin(p));
     fdas_status s = enqueue_search(p, ws, g, FDAS_IN_SERIES_F32, ws.series, ws.plane, ws.cands, ws.count, st);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(st, &graph);

@@ -208,7 +208,7 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *__res
 
 __global__ __launch_bounds__(256) void k_cand_finalize(const DevCand *__restrict__ dc,
                                                        const uint32_t *__restrict__ order,
-                                                       const uint32_t *__restrict__ count, uint32_t cap,
+                                                       const uint32_t *__restrict__ count, uint32_t cap, int cpb,
                                                        double zmax, double dz, fdas_cand *__restrict__ out) {
     const uint32_t n = clamp_count(count, cap);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_cand_finalize(const DevCand *__restrict
         o.k = c.k;
         o.iz = c.iz;
         o.nharm = c.nharm;
-        o.r = double(c.k) / double(c.nharm);
+        o.r = double(c.k) / (double(c.nharm) * double(cpb));
         o.z = (-zmax + double(c.iz) * dz) / double(c.nharm);
         o.power = c.power;
         o.sigma = float(significance_d(double(c.power), c.nharm));
@@ -234,7 +234,7 @@ size_t cand_sort_scratch_bytes(uint32_t cap) {
 }
 
 hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch, int nz,
-                                    int64_t nb, double zmax, double dz, fdas_cand *out, hipStream_t st) {
+                                    int64_t nb, int cpb, double zmax, double dz, fdas_cand *out, hipStream_t st) {
     if (cap == 0) return hipSuccess;
     int bk = 1, bz = 1;
     while ((int64_t(1) << bk) < nb) ++bk;
@@ -268,7 +268,7 @@ hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, ui
         v0 = v1;
         v1 = tv;
     }
-    hipLaunchKernelGGL(k_cand_finalize, dim3(grid), dim3(256), 0, st, dc, v0, count, cap, zmax, dz, out);
+    hipLaunchKernelGGL(k_cand_finalize, dim3(grid), dim3(256), 0, st, dc, v0, count, cap, cpb, zmax, dz, out);
     return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ namespace fdas {
 // Per-length geometry.
 struct Geometry {
     int64_t nsamp = 0, nb = 0, L = 0, nseg = 0, nblk = 0;
+    int64_t ncol = 0;  // plane columns: nb, or 2 nb for a half-bin plane
 };
 
 // Device buffers for one series in flight (sized for `nsamp`).
@@ -62,6 +63,7 @@ struct fdas_plan_s {
     float code_inv = 1.f;       // 1 / delta of the screening codes
     uint32_t code_thr[5] = {};  // screen thresholds in code units
     float2 *d_bank = nullptr;  // nz x S, segment domain, scaled by 1/S (FFT correlator)
+    float2 *d_bank_half = nullptr;  // the same for the half-bin offsets (interbin)
     void *d_gemm = nullptr;    // template matrix of the matrix correlator
     int32_t corr = 0;          // FDAS_CORR_*
     int num_cu = 256;          // compute units of the device (matrix correlator grid)
@@ -89,9 +91,11 @@ void set_error(const std::string &msg);
 fdas_status hip_fail(fdas_plan_s *plan, hipError_t e, const char *what);
 fdas_status validate_opts(const fdas_opts &o);
 fdas_status check_nsamp(int64_t nsamp, int32_t seg, int32_t h);
-Geometry make_geometry(int64_t nsamp, int32_t S, int32_t h, int32_t W);
+// Plane columns per frequency bin: 2 for a half-bin plane.
+inline int cols_per_bin(const fdas_plan_s *p) { return p->opts.interbin ? 2 : 1; }
+Geometry make_geometry(int64_t nsamp, int32_t S, int32_t h, int32_t W, int cpb);
 int64_t series_bytes(const Geometry &g, int32_t S, int32_t nz);
-int64_t candidate_bytes(const fdas_plan_s *p, int64_t nb);
+int64_t candidate_bytes(const fdas_plan_s *p, const Geometry &g);
 fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp);
 void destroy_workspace(Workspace &ws);
 fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &g, int32_t in_kind,

@@ -63,6 +63,14 @@ fdas_status validate_opts(const fdas_opts &o) {
         set_error("opts.refine_levels must be in [0, 20]");
         return FDAS_E_INVAL;
     }
+    if (o.interbin != 0 && o.interbin != 1) {
+        set_error("opts.interbin must be 0 or 1");
+        return FDAS_E_INVAL;
+    }
+    if (o.interbin && o.correlator != FDAS_CORR_FFT_F32) {
+        set_error("the half-bin plane needs the FFT correlator");
+        return FDAS_E_INVAL;
+    }
     return FDAS_OK;
 }
 
@@ -77,10 +85,11 @@ fdas_status check_nsamp(int64_t nsamp, int32_t seg, int32_t h) {
 }
 
 // Geometry of one series length under a plan's segment length.
-Geometry make_geometry(int64_t nsamp, int32_t S, int32_t h, int32_t W) {
+Geometry make_geometry(int64_t nsamp, int32_t S, int32_t h, int32_t W, int cpb) {
     Geometry g;
     g.nsamp = nsamp;
     g.nb = nsamp / 2;
+    g.ncol = g.nb * cpb;
     g.L = (S - 2 * h) & ~3;  // a multiple of 4: store chunks and code blocks never straddle two segments
     g.nseg = (g.nb + g.L - 1) / g.L;
     g.nblk = (g.nb + W - 1) / W;
@@ -91,16 +100,16 @@ Geometry make_geometry(int64_t nsamp, int32_t S, int32_t h, int32_t W) {
 // spectra, plane and its screening codes) for a given geometry.
 int64_t series_bytes(const Geometry &g, int32_t S, int32_t nz) {
     const int64_t M = g.nb;
-    return 3 * M * 8 + g.nblk * 8 + g.nseg * int64_t(S) * 8 + int64_t(nz) * g.nb * 4 + int64_t(nz) * (g.nb / 2);
+    return 3 * M * 8 + g.nblk * 8 + g.nseg * int64_t(S) * 8 + int64_t(nz) * g.ncol * 4 + int64_t(nz) * (g.ncol / 2);
 }
 
 // Device bytes of the per-series buffers that depend on the plan's options
 // (candidate buffers, harmonic-sum lists, the matrix correlator's spectrum)
-// for a series of nb bins.
-int64_t candidate_bytes(const fdas_plan_s *p, int64_t nb) {
+// for a series of the given geometry.
+int64_t candidate_bytes(const fdas_plan_s *p, const Geometry &g) {
     const uint32_t cap = p->cand_cap;
     return int64_t(cap) * int64_t(sizeof(DevCand) + sizeof(fdas_cand)) + int64_t(cand_sort_scratch_bytes(cap)) +
-           int64_t(harmsum_scratch_bytes(p->nz, nb, p->hit_cap, p->group_cap)) + 64 + (p->corr ? nb * 4 : 0);
+           int64_t(harmsum_scratch_bytes(p->nz, g.ncol, p->hit_cap, p->group_cap)) + 64 + (p->corr ? g.nb * 4 : 0);
 }
 
 // Run the whole per-series path on `st`, writing the plane into `plane` and
@@ -137,7 +146,8 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
         e = launch_segfft(X, med, p->W, g.nb, p->log2s, p->h, g.nseg, ws.seg, st);
         if (e != hipSuccess) return hip_fail(p, e, "segment DFT");
         if ((e = mark(3)) != hipSuccess) return hip_fail(p, e, "timing event");
-        e = launch_correlate(ws.seg, p->d_bank, p->nz, p->tpb, g.nb, p->log2s, p->h, g.nseg, plane, ws.codes,
+        e = launch_correlate(ws.seg, p->d_bank, p->d_bank_half, p->nz, p->tpb, g.nb, p->log2s, p->h, g.nseg, plane,
+                             ws.codes,
                              p->code_inv, st);
         if (e != hipSuccess) return hip_fail(p, e, "correlate");
     } else {
@@ -151,16 +161,17 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
     if ((e = mark(4)) != hipSuccess) return hip_fail(p, e, "timing event");
     e = launch_zero_u32(dcount, 6, st);
     if (e != hipSuccess) return hip_fail(p, e, "zero counter");
-    e = launch_harmsum(plane, ws.codes, p->nz, g.nb, p->izc, p->opts.nharm_max, p->thr_f, p->code_thr, ws.hits,
+    e = launch_harmsum(plane, ws.codes, p->nz, g.ncol, p->izc, p->opts.nharm_max, p->thr_f, p->code_thr, ws.hits,
                        p->hit_cap, p->group_cap, dcands, dcount, p->cand_cap, st);
     if (e != hipSuccess) return hip_fail(p, e, "harmonic sum");
-    e = launch_finish_candidates(dcands, dcount, p->cand_cap, ws.sort, p->nz, g.nb, p->zmax, p->dz, ws.final, st);
+    e = launch_finish_candidates(dcands, dcount, p->cand_cap, ws.sort, p->nz, g.ncol, cols_per_bin(p), p->zmax, p->dz,
+                                 ws.final, st);
     if (e != hipSuccess) return hip_fail(p, e, "candidate sort");
     if ((e = mark(5)) != hipSuccess) return hip_fail(p, e, "timing event");
     if (p->opts.refine_levels > 0) {
         // four workgroups per compute unit, looping over the records
-        e = launch_refine(X, med, p->W, g.nb, p->h, p->izc, p->dz, p->zmax, p->opts.refine_levels, dcount,
-                          p->cand_cap, ws.final, 4 * p->num_cu, st);
+        e = launch_refine(X, med, p->W, g.nb, p->h, p->izc, p->dz, p->zmax, cols_per_bin(p), p->opts.refine_levels,
+                          dcount, p->cand_cap, ws.final, 4 * p->num_cu, st);
         if (e != hipSuccess) return hip_fail(p, e, "candidate refinement");
     }
     if ((e = mark(6)) != hipSuccess) return hip_fail(p, e, "timing event");
@@ -224,7 +235,7 @@ static void free_workspace(Workspace &ws) {
 }
 
 fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp) {
-    const Geometry g = make_geometry(nsamp, p->S, p->h, p->W);
+    const Geometry g = make_geometry(nsamp, p->S, p->h, p->W, cols_per_bin(p));
     const int64_t M = g.nb;
     hipError_t e;
 #define FDAS_ALLOC(ptr, bytes)                                                  \
@@ -240,13 +251,13 @@ fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp) {
     FDAS_ALLOC(ws.X, M * 8);
     FDAS_ALLOC(ws.med, g.nblk * 8);
     FDAS_ALLOC(ws.seg, g.nseg * int64_t(p->S) * 8);
-    FDAS_ALLOC(ws.plane, int64_t(p->nz) * g.nb * 4);
-    FDAS_ALLOC(ws.codes, int64_t(p->nz) * (g.nb / 2));
+    FDAS_ALLOC(ws.plane, int64_t(p->nz) * g.ncol * 4);
+    FDAS_ALLOC(ws.codes, int64_t(p->nz) * (g.ncol / 2));
     if (p->corr != FDAS_CORR_FFT_F32) FDAS_ALLOC(ws.xl, g.nb * 4);
     FDAS_ALLOC(ws.cands, int64_t(p->cand_cap) * int64_t(sizeof(DevCand)));
     FDAS_ALLOC(ws.count, 64);
     FDAS_ALLOC(ws.sort, cand_sort_scratch_bytes(p->cand_cap));
-    FDAS_ALLOC(ws.hits, harmsum_scratch_bytes(p->nz, g.nb, p->hit_cap, p->group_cap));
+    FDAS_ALLOC(ws.hits, harmsum_scratch_bytes(p->nz, g.ncol, p->hit_cap, p->group_cap));
     FDAS_ALLOC(ws.final, int64_t(p->cand_cap) * int64_t(sizeof(fdas_cand)));
 #undef FDAS_ALLOC
     e = hipHostMalloc(reinterpret_cast<void **>(&ws.h_count), 64, hipHostMallocDefault);
@@ -315,15 +326,15 @@ fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, 
         set_error("the matrix correlators need h <= 271 (zmax <= 510)");
         return FDAS_E_INVAL;
     }
+    const int64_t cells_plane = int64_t(bank->nz) * (nsamp / 2) * cols_per_bin(p);
     p->cand_cap = uint32_t(o.cand_capacity > 0
                                ? o.cand_capacity
-                               : std::min<int64_t>(int64_t(1) << 22,
-                                                   std::max<int64_t>(int64_t(1) << 16, int64_t(bank->nz) * (nsamp / 2) / 256)));
+                               : std::min<int64_t>(int64_t(1) << 22, std::max<int64_t>(int64_t(1) << 16, cells_plane / 256)));
     // Bins the harmonic-sum screen may pass on: 4 x the candidate capacity,
     // and with the automatic capacity at least every bin of planes up to 2^24
     // bins (dense low-threshold searches flag most blocks).
     int64_t cells = int64_t(p->cand_cap) * 4;
-    if (o.cand_capacity <= 0) cells = std::max<int64_t>(cells, std::min<int64_t>(int64_t(bank->nz) * (nsamp / 2), int64_t(1) << 24));
+    if (o.cand_capacity <= 0) cells = std::max<int64_t>(cells, std::min<int64_t>(cells_plane, int64_t(1) << 24));
     p->hit_cap = uint32_t(std::min<int64_t>(cells, int64_t(1) << 30));
     p->group_cap = std::max<uint32_t>(p->hit_cap / 2, 1u);
     int levels = 0;
@@ -373,31 +384,50 @@ fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, 
     }
     // Template bank in the segment domain: taps wrapped circularly (q >= 0 at
     // n = q, q < 0 at n = S + q), FP64 DFT, times 1/S, rounded to float32.
+    // With interbin a second bank holds the taps of the half-bin offsets.
     const int32_t S = seg, ntap = 2 * p->h + 1;
     std::vector<float2> host(size_t(p->nz) * S);
-    std::vector<cd> t(S);
-    for (int32_t iz = 0; iz < p->nz; ++iz) {
+    std::vector<cd> t(S), htaps(static_cast<size_t>(ntap));
+    auto to_segment_domain = [&](const cd *taps, int32_t iz) {
         std::fill(t.begin(), t.end(), cd(0.0, 0.0));
-        for (int32_t q = -p->h; q <= p->h; ++q) t[size_t((q + S) % S)] = bank->taps[size_t(iz) * ntap + (q + p->h)];
+        for (int32_t q = -p->h; q <= p->h; ++q) t[size_t((q + S) % S)] = taps[q + p->h];
         fft_inplace(t, -1);
         for (int32_t f = 0; f < S; ++f) {
             const cd v = t[size_t(f)] / double(S);
             host[size_t(iz) * S + f] = make_float2(float(v.real()), float(v.imag()));
         }
-    }
-    e = hipMalloc(reinterpret_cast<void **>(&p->d_bank), host.size() * sizeof(float2));
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
+    };
+    auto upload = [&](float2 **dst, const char *what) -> fdas_status {
+        hipError_t er = hipMalloc(reinterpret_cast<void **>(dst), host.size() * sizeof(float2));
+        if (er != hipSuccess) {
+            (void)hipGetLastError();
+            *dst = nullptr;
+            set_error(std::string("hipMalloc ") + what + ": " + hipGetErrorString(er));
+            return FDAS_E_NOMEM;
+        }
+        er = hipMemcpy(*dst, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice);
+        if (er != hipSuccess) {
+            set_error(std::string("upload ") + what + ": " + hipGetErrorString(er));
+            return FDAS_E_DEVICE;
+        }
+        return FDAS_OK;
+    };
+    auto fail = [&](fdas_status st) {
+        if (p->d_bank) (void)hipFree(p->d_bank);
+        if (p->d_bank_half) (void)hipFree(p->d_bank_half);
         delete p;
-        set_error(std::string("hipMalloc bank: ") + hipGetErrorString(e));
-        return FDAS_E_NOMEM;
-    }
-    e = hipMemcpy(p->d_bank, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        (void)hipFree(p->d_bank);
-        delete p;
-        set_error(std::string("upload bank: ") + hipGetErrorString(e));
-        return FDAS_E_DEVICE;
+        return st;
+    };
+    for (int32_t iz = 0; iz < p->nz; ++iz) to_segment_domain(&bank->taps[size_t(iz) * ntap], iz);
+    fdas_status ust = upload(&p->d_bank, "bank");
+    if (ust != FDAS_OK) return fail(ust);
+    if (o.interbin) {
+        for (int32_t iz = 0; iz < p->nz; ++iz) {
+            template_taps_half(fdas_bank_z(bank, iz), p->h, htaps.data());
+            to_segment_domain(htaps.data(), iz);
+        }
+        ust = upload(&p->d_bank_half, "half-bin bank");
+        if (ust != FDAS_OK) return fail(ust);
     }
     *out = p;
     return FDAS_OK;
@@ -513,12 +543,14 @@ int64_t fdas_plan_nbins(const fdas_plan_t *plan) { return plan ? plan->nsamp / 2
 
 int64_t fdas_plan_device_bytes(const fdas_plan_t *plan) {
     if (!plan) return 0;
-    int64_t b = plan->corr == FDAS_CORR_FFT_F32 ? int64_t(plan->nz) * plan->S * 8
+    int64_t b = plan->corr == FDAS_CORR_FFT_F32 ? int64_t(plan->nz) * plan->S * 8 * cols_per_bin(plan)
                                                 : int64_t(gemm_bank_bytes(plan->nz, plan->h));
-    for (const Workspace &ws : plan->ws)
-        if (ws.nsamp)
-            b += series_bytes(make_geometry(ws.nsamp, plan->S, plan->h, plan->W), plan->S, plan->nz) +
-                 candidate_bytes(plan, ws.nsamp / 2);
+    for (const Workspace &ws : plan->ws) {
+        if (ws.nsamp) {
+            const Geometry g = make_geometry(ws.nsamp, plan->S, plan->h, plan->W, cols_per_bin(plan));
+            b += series_bytes(g, plan->S, plan->nz) + candidate_bytes(plan, g);
+        }
+    }
     return b;
 }
 
@@ -540,6 +572,7 @@ void fdas_plan_destroy(fdas_plan_t *plan) {
     for (auto &m : plan->graphs)
         for (auto &kv : m) (void)hipGraphExecDestroy(kv.second);
     if (plan->d_bank) (void)hipFree(plan->d_bank);
+    if (plan->d_bank_half) (void)hipFree(plan->d_bank_half);
     if (plan->d_gemm) (void)hipFree(plan->d_gemm);
     delete plan;
 }
@@ -564,7 +597,7 @@ fdas_status fdas_search(fdas_plan_t *plan, int32_t in_kind, const void *in_dev, 
     }
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     Workspace &ws = plan->ws[0];
-    const Geometry g = make_geometry(plan->nsamp, plan->S, plan->h, plan->W);
+    const Geometry g = make_geometry(plan->nsamp, plan->S, plan->h, plan->W, cols_per_bin(plan));
     float *plane = plane_dev ? plane_dev : ws.plane;
     const bool timed = plan->timing;
     fdas_status s = enqueue_search(plan, ws, g, in_kind, in_dev, plane, ws.cands, ws.count, st, timed);
@@ -716,7 +749,7 @@ fdas_status fdas_refine(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t 
     if ((e = hipMemcpyAsync(dc, cands, bytes, hipMemcpyHostToDevice, st)) == hipSuccess &&
         (e = hipMemcpyAsync(dn, &nn, sizeof(nn), hipMemcpyHostToDevice, st)) == hipSuccess &&
         (e = launch_refine(plan->last_X, plan->last_med, plan->W, plan->last_nb, plan->h, plan->izc, plan->dz,
-                           plan->zmax, levels, dn, nn, dc, 4 * plan->num_cu, st)) == hipSuccess &&
+                           plan->zmax, cols_per_bin(plan), levels, dn, nn, dc, 4 * plan->num_cu, st)) == hipSuccess &&
         (e = hipMemcpyAsync(cands, dc, bytes, hipMemcpyDeviceToHost, st)) == hipSuccess) {
         e = hipStreamSynchronize(st);
     }

@@ -122,6 +122,18 @@ void template_taps(double z, int32_t h, cd *out) {
     for (int32_t i = 0; i < 2 * h + 1; ++i) out[i] *= inv;
 }
 
+void template_taps_half(double z, int32_t h, cd *out) {
+    double e = 0.0;
+    for (int32_t q = -h; q < h; ++q) {
+        const cd a = accel_response(double(q) + 0.5, z);
+        out[q + h] = std::conj(a);
+        e += std::norm(a);
+    }
+    out[2 * h] = cd(0.0, 0.0);
+    const double inv = 1.0 / std::sqrt(e);
+    for (int32_t i = 0; i < 2 * h; ++i) out[i] *= inv;
+}
+
 void fft_inplace(std::vector<cd> &a, int sign) {
     const size_t n = a.size();
     if (n == 0 || (n & (n - 1))) throw std::invalid_argument("fft length must be a power of two");

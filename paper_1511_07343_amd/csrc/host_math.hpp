@@ -24,6 +24,10 @@ int32_t template_halfwidth(double zmax);
 
 // Taps of one template: conj(A(q, z)) / ||A||, q = -h..h (2h+1 values).
 void template_taps(double z, int32_t h, cd *out);
+// Half-bin taps: out[q + h] = conj(A(q + 1/2, z)) / norm for q = -h .. h-1 (the
+// 2h offsets within h of a point halfway between bins), out[2h] = 0; the norm
+// is taken over those 2h taps.
+void template_taps_half(double z, int32_t h, cd *out);
 
 // In-place unnormalised FFT, sign -1 forward (e^{-2 pi i n k / n}) or +1.
 void fft_inplace(std::vector<cd> &a, int sign);

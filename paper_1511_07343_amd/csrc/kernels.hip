@@ -254,11 +254,18 @@ __global__ __launch_bounds__(256) void k_normalise(const float2 *__restrict__ X,
 // evenly over the 8 XCDs, one group of blocks over all segments, with the
 // group's templates kept in its own L2 and each segment spectrum read by the
 // group's blocks while still resident.
-template <int LOG2S>
+//
+// INTERBIN: every template is run twice, with the integer-offset bank and
+// with the half-bin bank, into a plane of 2 nb columns (column 2k = bin k,
+// 2k + 1 = k + 1/2) and one code per column pair.  The first pass parks its
+// 4-point chunk in the first half of the chunk's 8-column span; the second
+// pass (same thread, same chunk) reads it back and writes the interleaved
+// span and the codes.
+template <int LOG2S, bool INTERBIN>
 __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
-    const float2 *__restrict__ segspec, const float2 *__restrict__ bank, int nz, int tpb, int64_t nb,
-    int h, int64_t nseg, int64_t total, int64_t per, int grp, float *__restrict__ plane,
-    uint8_t *__restrict__ codes, float code_inv) {
+    const float2 *__restrict__ segspec, const float2 *__restrict__ bank, const float2 *__restrict__ bank_half,
+    int nz, int tpb, int64_t nb, int h, int64_t nseg, int64_t total, int64_t per, int grp,
+    float *__restrict__ plane, uint8_t *__restrict__ codes, float code_inv) {
     using Sh = FftShape<LOG2S, corr_threads(LOG2S)>;
     __shared__ float2 lds[Sh::LDS_FLOAT2];
     const int t = threadIdx.x;
@@ -283,18 +290,21 @@ __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
     // points [h, nend) of this segment are plane columns [s L, min(s L + L, nb))
     const int nend = int(min(int64_t(h) + L, nb - kbase));
     const int sh = int(((kbase % 4) + 4) % 4);  // plane row offset of point 0 modulo 4
-    for (int iz = iz0; iz < iz1; ++iz) {
+    constexpr int PASSES = INTERBIN ? 2 : 1;
+    for (int it = iz0 * PASSES; it < iz1 * PASSES; ++it) {
+        const int iz = INTERBIN ? (it >> 1) : it;
+        const bool second = INTERBIN && (it & 1);
         // Keep the per-point offsets inside the loop: hoisting the 32 addresses
         // of each operand out of it would cost more registers than recomputing.
         int to = t;
         asm volatile("" : "+v"(to));
-        const float2 *__restrict__ bz = bank + int64_t(iz) * Sh::S;
+        const float2 *__restrict__ bz = (second ? bank_half : bank) + int64_t(iz) * Sh::S;
         float2 v[Sh::R];
 #pragma unroll
         for (int m = 0; m < Sh::R; ++m) v[m] = cmul(sp[to + Sh::NT * m], bz[to + Sh::NT * m]);
         fft_wg<Sh, +1>(v, lds, tw, t);
-        float *__restrict__ row = plane + int64_t(iz) * nb + kbase;
-        uint8_t *__restrict__ qrow = codes + int64_t(iz) * (nb / 2);
+        float *__restrict__ row = plane + int64_t(iz) * nb * PASSES + kbase * PASSES;
+        uint8_t *__restrict__ qrow = codes + int64_t(iz) * (nb * PASSES / 2);
         // Powers through LDS so that each thread stores 4 consecutive
         // points: point n sits at LDS index n + sh, which puts chunk c
         // (indices 4c .. 4c+3) on a 16-byte boundary of the plane row, i.e.
@@ -309,9 +319,21 @@ __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
             const int n0 = 4 * c - sh;
             const float4 p4 = *reinterpret_cast<const float4 *>(lf + 4 * c);
             if (n0 >= h && n0 + 4 <= nend) {
-                __builtin_nontemporal_store(__builtin_bit_cast(f32x4v, p4), reinterpret_cast<f32x4v *>(row + n0));
-                __builtin_nontemporal_store(block_codes4(p4, code_inv),
-                                            reinterpret_cast<uint16_t *>(qrow + ((kbase + n0) >> 1)));
+                if constexpr (!INTERBIN) {
+                    __builtin_nontemporal_store(__builtin_bit_cast(f32x4v, p4), reinterpret_cast<f32x4v *>(row + n0));
+                    __builtin_nontemporal_store(block_codes4(p4, code_inv),
+                                                reinterpret_cast<uint16_t *>(qrow + ((kbase + n0) >> 1)));
+                } else if (!second) {
+                    *reinterpret_cast<float4 *>(row + 2 * n0) = p4;  // parked until the half-bin pass
+                } else {
+                    const float4 b4 = *reinterpret_cast<const float4 *>(row + 2 * n0);
+                    const float4 lo = make_float4(b4.x, p4.x, b4.y, p4.y), hi = make_float4(b4.z, p4.z, b4.w, p4.w);
+                    __builtin_nontemporal_store(__builtin_bit_cast(f32x4v, lo), reinterpret_cast<f32x4v *>(row + 2 * n0));
+                    __builtin_nontemporal_store(__builtin_bit_cast(f32x4v, hi),
+                                                reinterpret_cast<f32x4v *>(row + 2 * n0 + 4));
+                    const uint32_t q = uint32_t(block_codes4(lo, code_inv)) | (uint32_t(block_codes4(hi, code_inv)) << 16);
+                    __builtin_nontemporal_store(q, reinterpret_cast<uint32_t *>(qrow + kbase + n0));
+                }
             }
         }
         __syncthreads();  // the next transform writes lds
@@ -836,8 +858,8 @@ hipError_t launch_normalise(const float2 *X, const double *med, int W, int64_t n
     return hipGetLastError();
 }
 
-hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, int tpb, int64_t nb,
-                            int log2s, int h, int64_t nseg, float *plane, uint8_t *codes, float code_inv,
+hipError_t launch_correlate(const float2 *segspec, const float2 *bank, const float2 *bank_half, int nz, int tpb,
+                            int64_t nb, int log2s, int h, int64_t nseg, float *plane, uint8_t *codes, float code_inv,
                             hipStream_t st) {
     if (nseg <= 0 || nz <= 0) return hipSuccess;
     if (tpb <= 0) return hipErrorInvalidValue;
@@ -848,9 +870,13 @@ hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, i
     if (grid > 0x7fffffff) return hipErrorInvalidValue;
     // template blocks per group: the blocks of one XCD when they split evenly
     const int grp = (nzb % kXcds == 0) ? int(nzb / kXcds) : 1;
-#define CALL(L)                                                                                       \
-    hipLaunchKernelGGL((k_correlate<L>), dim3(unsigned(grid)), dim3(corr_threads(L)), 0, st, segspec, bank, \
-                       nz, tpb, nb, h, nseg, total, per, grp, plane, codes, code_inv);
+#define CALL(L)                                                                                          \
+    if (bank_half)                                                                                       \
+        hipLaunchKernelGGL((k_correlate<L, true>), dim3(unsigned(grid)), dim3(corr_threads(L)), 0, st, segspec, \
+                           bank, bank_half, nz, tpb, nb, h, nseg, total, per, grp, plane, codes, code_inv);     \
+    else                                                                                                 \
+        hipLaunchKernelGGL((k_correlate<L, false>), dim3(unsigned(grid)), dim3(corr_threads(L)), 0, st, segspec, \
+                           bank, bank_half, nz, tpb, nb, h, nseg, total, per, grp, plane, codes, code_inv);
     FDAS_SWITCH_LOG2(log2s, CALL)
 #undef CALL
     return hipGetLastError();

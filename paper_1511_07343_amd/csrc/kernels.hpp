@@ -50,8 +50,10 @@ hipError_t launch_normalise(const float2 *X, const double *med, int W, int64_t n
 //   plane[iz][s L + n - h] = |y[n]|^2 for n in [h, h + L), inside [0, nb),
 // and beside it the screening codes of 2-bin blocks (nz x nb/2 bytes)
 //   codes[iz][b] = max_{k in {2b, 2b + 1}} min(255, ceil(plane[iz][k] * code_inv)).
-hipError_t launch_correlate(const float2 *segspec, const float2 *bank, int nz, int tpb, int64_t nb,
-                            int log2s, int h, int64_t nseg, float *plane, uint8_t *codes, float code_inv,
+// With bank_half (the half-bin offsets' bank) the plane has 2 nb columns,
+// 2k from bank and 2k + 1 from bank_half, and nz x nb codes of column pairs.
+hipError_t launch_correlate(const float2 *segspec, const float2 *bank, const float2 *bank_half, int nz, int tpb,
+                            int64_t nb, int log2s, int h, int64_t nseg, float *plane, uint8_t *codes, float code_inv,
                             hipStream_t st);
 
 // Matrix-core correlator (BF16 or FP16 operands, FP32 accumulation).
@@ -93,23 +95,25 @@ hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int6
                           uint32_t group_cap, DevCand *cands, uint32_t *count, uint32_t cap, hipStream_t st);
 
 // Candidate finishing: sort the first min(*count, cap) records by
-// (nharm, k, iz) (k < nb, iz < nz) and write public records (r, z, FP64
-// significance) to out.
+// (nharm, k, iz) (k < nb plane columns, iz < nz) and write public records
+// (r = k / (nharm cpb) with cpb plane columns per bin, z, FP64 significance)
+// to out.
 // scratch: cand_sort_scratch_bytes(cap) bytes.
 size_t cand_sort_scratch_bytes(uint32_t cap);
 hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch, int nz,
-                                    int64_t nb, double zmax, double dz, fdas_cand *out, hipStream_t st);
+                                    int64_t nb, int cpb, double zmax, double dz, fdas_cand *out, hipStream_t st);
 
 // Candidate refinement (Fourier interpolation off the grid): for each of the
 // first min(*count, cap) public records, a pattern search over the
 // fundamental (r, z) for the largest S(r, z) = sum_{j=1}^{nh} P(j r, j z),
 // P the correlation power with the response evaluated at the exact offset
-// and drift; levels step halvings from half a grid cell.  r, z, power and
+// and drift, starting from r = k / (nh cpb) (cpb plane columns per bin);
+// levels step halvings from half a grid cell.  r, z, power and
 // sigma of the records are replaced by those of the final point.  The
 // spectrum is X scaled by sqrt(ln2 / m(k)) (X itself when med is NULL), as in
 // the search.  A persistent grid of `workgroups` workgroups.
 hipError_t launch_refine(const float2 *X, const double *med, int W, int64_t nb, int h, int izc, double dz,
-                         double zmax, int levels, const uint32_t *count, uint32_t cap, fdas_cand *cands,
+                         double zmax, int cpb, int levels, const uint32_t *count, uint32_t cap, fdas_cand *cands,
                          int workgroups, hipStream_t st);
 // out[i] = S(r[i], z[i]) with nh[i] harmonics (NaN when nh[i] is not in 1..16),
 // device arrays of n entries.

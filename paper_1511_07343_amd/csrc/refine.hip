@@ -238,13 +238,13 @@ __device__ void eval_points(const Spectrum &sp, int h, int nh, int npts, double 
 }
 
 // One workgroup per candidate (persistent grid): start at the fundamental
-// r = k / nh, z = ((iz - izc) dz) / nh, then per level l = 1 .. levels move
+// r = k / (nh cpb), z = ((iz - izc) dz) / nh (cpb = 2 on a half-bin plane), then per level l = 1 .. levels move
 // to the best of the 8 neighbours at steps (2^-l / nh, (dz 2^-l) / nh) when
 // it is strictly larger than the centre (earlier points win ties); points
 // whose top harmonic drifts beyond the bank (|nh z| > zmax) are skipped.
 __global__ __launch_bounds__(RF_THREADS) void k_refine(Spectrum sp, int h, int izc, double dz, double zmax,
-                                                       int levels, const uint32_t *__restrict__ count, uint32_t cap,
-                                                       fdas_cand *__restrict__ cands) {
+                                                       int cpb, int levels, const uint32_t *__restrict__ count,
+                                                       uint32_t cap, fdas_cand *__restrict__ cands) {
     __shared__ double pw[RF_POINTS * RF_MAX_NH];
     __shared__ double S[RF_POINTS];
     const uint32_t n = min(*count, cap);
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(RF_THREADS) void k_refine(Spectrum sp, int h, int i
         const int iz = cands[c].iz;
         const int nh = cands[c].nharm;
         if (nh < 1 || nh > RF_MAX_NH) continue;  // uniform over the workgroup
-        double r = double(k) / double(nh);
+        double r = double(k) / (double(nh) * double(cpb));
         double z = (double(iz - izc) * dz) / double(nh);
         double best = 0.0;
         // level 0 evaluates the centre alone
@@ -331,12 +331,12 @@ Spectrum make_spectrum(const float2 *X, const double *med, int W, int64_t nb) {
 }  // namespace
 
 hipError_t launch_refine(const float2 *X, const double *med, int W, int64_t nb, int h, int izc, double dz,
-                         double zmax, int levels, const uint32_t *count, uint32_t cap, fdas_cand *cands,
+                         double zmax, int cpb, int levels, const uint32_t *count, uint32_t cap, fdas_cand *cands,
                          int workgroups, hipStream_t st) {
     if (cap == 0 || levels <= 0) return hipSuccess;
     if (levels > 30 || workgroups <= 0 || nb <= 0 || W <= 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_refine, dim3(unsigned(workgroups)), dim3(RF_THREADS), 0, st,
-                       make_spectrum(X, med, W, nb), h, izc, dz, zmax, levels, count, cap, cands);
+                       make_spectrum(X, med, W, nb), h, izc, dz, zmax, cpb, levels, count, cap, cands);
     hipLaunchKernelGGL(k_refine_sigma, dim3(unsigned(workgroups)), dim3(256), 0, st, count, cap, cands);
     return hipGetLastError();
 }

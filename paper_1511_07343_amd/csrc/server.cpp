@@ -81,8 +81,8 @@ struct fdas_server_s {
 namespace fdas {
 
 static int64_t buffer_bytes(const fdas_plan_s *core, int64_t nsamp) {
-    const Geometry g = make_geometry(nsamp, core->S, core->h, core->W);
-    return series_bytes(g, core->S, core->nz) + nsamp * 4 + candidate_bytes(core, g.nb);
+    const Geometry g = make_geometry(nsamp, core->S, core->h, core->W, cols_per_bin(core));
+    return series_bytes(g, core->S, core->nz) + nsamp * 4 + candidate_bytes(core, g);
 }
 
 static void free_buffers(Buffers *b) {
@@ -201,7 +201,8 @@ static void scheduler(fdas_server_s *sv) {
             hipError_t e = hipMemcpyAsync(buf->series, req.host, size_t(req.nsamp) * 4, hipMemcpyHostToDevice, st);
             fdas_status s = FDAS_OK;
             if (e == hipSuccess) {
-                const Geometry g = make_geometry(req.nsamp, sv->core->S, sv->core->h, sv->core->W);
+                const Geometry g = make_geometry(req.nsamp, sv->core->S, sv->core->h, sv->core->W,
+                                                 cols_per_bin(sv->core));
                 s = enqueue_search(sv->core, buf->ws, g, FDAS_IN_SERIES_F32, buf->series, buf->ws.plane,
                                    buf->ws.cands, buf->ws.count, st);
                 if (s == FDAS_OK) e = hipMemcpyAsync(buf->ws.h_count, buf->ws.count, 24, hipMemcpyDeviceToHost, st);
