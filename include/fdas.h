@@ -25,8 +25,9 @@
  *     Nb = N/2 bins, bin 0 (DC) is zeroed and the Nyquist bin dropped.
  *   - The f-fdot plane is float32[nz][Nb], template-major (row iz holds all
  *     Nb frequency bins of template iz, contiguous in k); with
- *     fdas_opts.interbin it is float32[nz][2 Nb], column 2k holding bin k and
- *     column 2k + 1 the point k + 1/2 between bins k and k + 1.
+ *     fdas_opts.interbin it is float32[nz][2 Nb], row iz holding bins
+ *     k = 0 .. Nb-1 in its first Nb floats and the points k + 1/2 between
+ *     bins k and k + 1 in the next Nb.
  */
 #ifndef FDAS_H
 #define FDAS_H
@@ -90,11 +91,12 @@ typedef struct fdas_opts {
 /* Half-bin plane (interbin = 1), an extension past the paper's method: a
  * second template bank at offsets q + 1/2, T'_z[q] = conj(A(q + 1/2, z)) /
  * norm for q = -h .. h-1 (the 2h offsets within h of the half-bin point),
- * gives P(k + 1/2, z), interleaved with P(k, z) into a plane of 2 Nb columns
- * (the interpolated power of the refinement note below at r = k/2).  The
- * harmonic sums, thresholds and peaks then run on that plane with k in half
- * bins, so a tone between two bins loses at most sinc^2(1/4) = 0.81 of its
- * power to scalloping instead of sinc^2(1/2) = 0.41.  Twice the correlation
+ * gives P(k + 1/2, z) (the interpolated power of the refinement note below
+ * at r = k + 1/2), stored beside P(k, z) (see the plane layout above).  The
+ * harmonic sums, thresholds and peaks then run on the half-bin grid, point
+ * c = 2k or 2k + 1 for r = c / 2, with candidate k = c, so a tone between
+ * two bins keeps at least sinc^2(1/4) = 0.81 of its power on the grid
+ * instead of sinc^2(1/2) = 0.41.  Twice the correlation
  * work and plane memory.  FFT correlator only (INVAL with a matrix one). */
 
 /* Candidate refinement (refine_levels > 0), an extension past the paper's

@@ -226,7 +226,8 @@ def template_taps_half(zmax: float, dz: float, h: int | None = None):
 
 
 def interbin_plane(P: np.ndarray, P_half: np.ndarray) -> np.ndarray:
-    """Half-bin plane: column 2k = P[:, k] (bin k), 2k + 1 = P_half[:, k] (k + 1/2)."""
+    """Half-bin plane on the half-bin grid: column 2k = P[:, k] (bin k),
+    2k + 1 = P_half[:, k] (k + 1/2); the harmonic sums index it in half bins."""
     out = np.empty((P.shape[0], 2 * P.shape[1]), dtype=np.float64)
     out[:, 0::2] = P
     out[:, 1::2] = P_half

@@ -161,7 +161,7 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
     if ((e = mark(4)) != hipSuccess) return hip_fail(p, e, "timing event");
     e = launch_zero_u32(dcount, 6, st);
     if (e != hipSuccess) return hip_fail(p, e, "zero counter");
-    e = launch_harmsum(plane, ws.codes, p->nz, g.ncol, p->izc, p->opts.nharm_max, p->thr_f, p->code_thr, ws.hits,
+    e = launch_harmsum(plane, ws.codes, p->nz, g.ncol, p->opts.interbin ? g.nb : 0, p->izc, p->opts.nharm_max, p->thr_f, p->code_thr, ws.hits,
                        p->hit_cap, p->group_cap, dcands, dcount, p->cand_cap, st);
     if (e != hipSuccess) return hip_fail(p, e, "harmonic sum");
     e = launch_finish_candidates(dcands, dcount, p->cand_cap, ws.sort, p->nz, g.ncol, cols_per_bin(p), p->zmax, p->dz,

@@ -256,11 +256,11 @@ __global__ __launch_bounds__(256) void k_normalise(const float2 *__restrict__ X,
 // group's blocks while still resident.
 //
 // INTERBIN: every template is run twice, with the integer-offset bank and
-// with the half-bin bank, into a plane of 2 nb columns (column 2k = bin k,
-// 2k + 1 = k + 1/2) and one code per column pair.  The first pass parks its
-// 4-point chunk in the first half of the chunk's 8-column span; the second
-// pass (same thread, same chunk) reads it back and writes the interleaved
-// span and the codes.
+// with the half-bin bank, into a row of 2 nb floats (bins k in [0, nb), the
+// points k + 1/2 in [nb, 2 nb)) and one code per pair (k, k + 1/2).  The first
+// pass stores the codes of its own 4 points (one byte each); the second pass
+// (same thread, same chunk) reads that word back and keeps the larger code
+// of each pair.
 template <int LOG2S, bool INTERBIN>
 __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
     const float2 *__restrict__ segspec, const float2 *__restrict__ bank, const float2 *__restrict__ bank_half,
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
 #pragma unroll
         for (int m = 0; m < Sh::R; ++m) v[m] = cmul(sp[to + Sh::NT * m], bz[to + Sh::NT * m]);
         fft_wg<Sh, +1>(v, lds, tw, t);
-        float *__restrict__ row = plane + int64_t(iz) * nb * PASSES + kbase * PASSES;
+        float *__restrict__ row = plane + int64_t(iz) * nb * PASSES + (second ? nb : 0) + kbase;
         uint8_t *__restrict__ qrow = codes + int64_t(iz) * (nb * PASSES / 2);
         // Powers through LDS so that each thread stores 4 consecutive
         // points: point n sits at LDS index n + sh, which puts chunk c
@@ -319,20 +319,24 @@ __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
             const int n0 = 4 * c - sh;
             const float4 p4 = *reinterpret_cast<const float4 *>(lf + 4 * c);
             if (n0 >= h && n0 + 4 <= nend) {
+                __builtin_nontemporal_store(__builtin_bit_cast(f32x4v, p4), reinterpret_cast<f32x4v *>(row + n0));
                 if constexpr (!INTERBIN) {
-                    __builtin_nontemporal_store(__builtin_bit_cast(f32x4v, p4), reinterpret_cast<f32x4v *>(row + n0));
                     __builtin_nontemporal_store(block_codes4(p4, code_inv),
                                                 reinterpret_cast<uint16_t *>(qrow + ((kbase + n0) >> 1)));
-                } else if (!second) {
-                    *reinterpret_cast<float4 *>(row + 2 * n0) = p4;  // parked until the half-bin pass
                 } else {
-                    const float4 b4 = *reinterpret_cast<const float4 *>(row + 2 * n0);
-                    const float4 lo = make_float4(b4.x, p4.x, b4.y, p4.y), hi = make_float4(b4.z, p4.z, b4.w, p4.w);
-                    __builtin_nontemporal_store(__builtin_bit_cast(f32x4v, lo), reinterpret_cast<f32x4v *>(row + 2 * n0));
-                    __builtin_nontemporal_store(__builtin_bit_cast(f32x4v, hi),
-                                                reinterpret_cast<f32x4v *>(row + 2 * n0 + 4));
-                    const uint32_t q = uint32_t(block_codes4(lo, code_inv)) | (uint32_t(block_codes4(hi, code_inv)) << 16);
-                    __builtin_nontemporal_store(q, reinterpret_cast<uint32_t *>(qrow + kbase + n0));
+                    uint32_t q = uint32_t(power_code(p4.x, code_inv)) | (uint32_t(power_code(p4.y, code_inv)) << 8) |
+                                 (uint32_t(power_code(p4.z, code_inv)) << 16) |
+                                 (uint32_t(power_code(p4.w, code_inv)) << 24);
+                    uint32_t *__restrict__ qw = reinterpret_cast<uint32_t *>(qrow + kbase + n0);
+                    if (!second) {
+                        *qw = q;  // read back by the half-bin pass
+                    } else {
+                        const uint32_t a = *qw;
+                        uint32_t m = 0;
+#pragma unroll
+                        for (int b = 0; b < 32; b += 8) m |= max((a >> b) & 0xffu, (q >> b) & 0xffu) << b;
+                        __builtin_nontemporal_store(m, qw);
+                    }
                 }
             }
         }
@@ -375,16 +379,23 @@ __device__ __forceinline__ constexpr bool frac_used(int j) {
 }
 
 // All levels at one cell, loading its terms directly from the plane.
+// split > 0: a half-bin plane, whose column c (half bins) is stored at
+// c / 2 for even c and at split + c / 2 for odd c (split = bins per row).
 template <int LEVELS>
-__device__ __forceinline__ void cell_sums(const float *__restrict__ P, int64_t nb, int izc, int iz, int k,
-                                          float (&s)[5]) {
+__device__ __forceinline__ void cell_sums(const float *__restrict__ P, int64_t nb, int64_t split, int izc, int iz,
+                                          int k, float (&s)[5]) {
     float v[17];
     v[0] = 0.f;
     const int d = iz - izc;
     static_for<1, 17>([&](auto jc) {
         constexpr int j = decltype(jc)::value;
-        if constexpr (frac_used<LEVELS>(j)) v[j] = P[int64_t(frac_row(izc, d, j)) * nb + ((j * k + 8) >> 4)];
-        else v[j] = 0.f;
+        if constexpr (frac_used<LEVELS>(j)) {
+            const int64_t c = (j * k + 8) >> 4;
+            const int64_t col = split ? (c >> 1) + (c & 1) * split : c;
+            v[j] = P[int64_t(frac_row(izc, d, j)) * nb + col];
+        } else {
+            v[j] = 0.f;
+        }
     });
     nested_sums<LEVELS>(v, s);
 }
@@ -617,7 +628,8 @@ __device__ __forceinline__ uint32_t cell_index(const Group &r, int i) {
 // plane in the one summation order of nested_sums; cells reaching a threshold
 // at some level go to the hit list (one atomic per wave).
 template <int LEVELS>
-__global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int nz, int64_t nb, int izc, Thr thr,
+__global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int nz, int64_t nb, int64_t split,
+                                               int izc, Thr thr,
                                                const uint2 *__restrict__ blocks, uint32_t *__restrict__ cnt,
                                                uint32_t cell_cap, float *__restrict__ sums,
                                                uint32_t *__restrict__ hits) {
@@ -634,7 +646,7 @@ __global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int 
             const int iz = int(e.y);
             if (k < nb && iz < nz) {  // guards against entries of an overflowed list
                 float s[5];
-                cell_sums<LEVELS>(P, nb, izc, iz, int(k), s);
+                cell_sums<LEVELS>(P, nb, split, izc, iz, int(k), s);
                 float *__restrict__ o = sums + int64_t(c) * SUM_STRIDE;
 #pragma unroll
                 for (int l = 0; l <= LEVELS; ++l) {
@@ -888,13 +900,15 @@ size_t harmsum_scratch_bytes(int nz, int64_t nb, uint32_t cell_cap, uint32_t gro
            size_t(nz) * size_t(nb / SC_COLS) * sizeof(uint32_t);
 }
 
-hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int64_t nb, int izc, int nharm_max,
+hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int64_t nb, int64_t split, int izc,
+                          int nharm_max,
                           const float *thr_host, const uint32_t *code_thr, void *scratch, uint32_t cell_cap,
                           uint32_t group_cap, DevCand *cands, uint32_t *count, uint32_t cap, hipStream_t st) {
     int levels = 0;
     while ((1 << levels) < nharm_max) ++levels;
     if ((1 << levels) != nharm_max || levels > 4) return hipErrorInvalidValue;
     if (nb > (int64_t(1) << 26) || nb % SC_COLS != 0 || nz > 65535) return hipErrorInvalidValue;
+    if (split != 0 && 2 * split != nb) return hipErrorInvalidValue;
     Thr thr{};
     ScreenThr T{};
     for (int l = 0; l <= levels; ++l) {
@@ -914,7 +928,7 @@ hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int6
 #define CALL(LV)                                                                                                   \
     hipLaunchKernelGGL((k_screen<LV>), grid1, dim3(64 * SC_WAVES), 0, st, codes, nz, nb, izc, T, groups, blocks,    \
                        group_map, count, group_cap, cell_cap);                                                     \
-    hipLaunchKernelGGL((k_exact<LV>), dim3(grid2), dim3(256), 0, st, plane, nz, nb, izc, thr, blocks, count,        \
+    hipLaunchKernelGGL((k_exact<LV>), dim3(grid2), dim3(256), 0, st, plane, nz, nb, split, izc, thr, blocks, count, \
                        cell_cap, sums, hits);                                                                     \
     hipLaunchKernelGGL((k_peaks<LV>), dim3(grid2), dim3(256), 0, st, nz, nb, thr, groups, group_map, blocks, sums,  \
                        hits, count, group_cap, cell_cap, cands, cap);

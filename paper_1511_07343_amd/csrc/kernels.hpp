@@ -50,8 +50,10 @@ hipError_t launch_normalise(const float2 *X, const double *med, int W, int64_t n
 //   plane[iz][s L + n - h] = |y[n]|^2 for n in [h, h + L), inside [0, nb),
 // and beside it the screening codes of 2-bin blocks (nz x nb/2 bytes)
 //   codes[iz][b] = max_{k in {2b, 2b + 1}} min(255, ceil(plane[iz][k] * code_inv)).
-// With bank_half (the half-bin offsets' bank) the plane has 2 nb columns,
-// 2k from bank and 2k + 1 from bank_half, and nz x nb codes of column pairs.
+// With bank_half (the half-bin offsets' bank) each plane row holds 2 nb
+// floats, the bins k from bank in [0, nb) and the points k + 1/2 from
+// bank_half in [nb, 2 nb), and the nz x nb codes cover the pairs
+// (k, k + 1/2): codes[iz][k] = max of the two points' codes.
 hipError_t launch_correlate(const float2 *segspec, const float2 *bank, const float2 *bank_half, int nz, int tpb,
                             int64_t nb, int log2s, int h, int64_t nseg, float *plane, uint8_t *codes, float code_inv,
                             hipStream_t st);
@@ -87,10 +89,13 @@ hipError_t launch_corr_gemm(const uint32_t *xl, int64_t nb, int h, const void *b
 // start at 0: candidates are appended to cands (capacity cap) through
 // count[0]; count[1] counts bins reaching a threshold, count[4] and count[5]
 // listed bins and groups; count[2] is set to 1 if a list overflowed (the
-// candidates are then incomplete).  nb must be a multiple of 32, nz at most
-// 65535.
+// candidates are then incomplete).  nb (plane columns) must be a multiple of
+// 32, nz at most 65535.  split > 0 marks a half-bin plane stored as two
+// halves per row: column c (in half bins) at c / 2 for even c and at
+// split + c / 2 for odd c.
 size_t harmsum_scratch_bytes(int nz, int64_t nb, uint32_t cell_cap, uint32_t group_cap);
-hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int64_t nb, int izc, int nharm_max,
+hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int64_t nb, int64_t split, int izc,
+                          int nharm_max,
                           const float *thr_host, const uint32_t *code_thr, void *scratch, uint32_t cell_cap,
                           uint32_t group_cap, DevCand *cands, uint32_t *count, uint32_t cap, hipStream_t st);
 
