@@ -23,6 +23,9 @@ segmentation, no blocking:
 8. ``interp_power``, ``refine``  Fourier interpolation of the correlation at
                         fractional (r, z) and a pattern search around each
                         candidate (an extension past the paper's method).
+9. ``td_search``       the time-domain resampling search the paper names as
+                        the other method (Sec. 1): resample per acceleration,
+                        one long DFT each, harmonic sums along each spectrum.
 
 Parity pins for each function live in tests/test_oracle_*.py.
 """
@@ -68,6 +71,10 @@ __all__ = [
     "refine_start",
     "refine",
     "refine_endpoints",
+    "td_alphas",
+    "td_resample",
+    "td_harmonic_sum",
+    "td_search",
 ]
 
 LN2 = math.log(2.0)
@@ -586,3 +593,85 @@ def refine_endpoints(Xhat: np.ndarray, k: int, iz: int, nh: int, *, zmax: float,
             raise RuntimeError("refine_endpoints: too many near-tied paths")
         paths = [(rr, zz, s) for (rr, zz), s in nxt.items()]
     return {(r, z): s for r, z, s in paths}
+
+
+# --------------------------------------------------------------------------
+# 9. Time-domain resampling search (Sec. 1: the other acceleration search,
+#    resampling the series per acceleration, then one long DFT per trial)
+# --------------------------------------------------------------------------
+def td_alphas(alpha_max: float, nalpha: int) -> np.ndarray:
+    """Acceleration trials alpha_i = -alpha_max + i d, d = 2 alpha_max / (nalpha - 1)
+    (one trial, alpha = 0, when nalpha is 1).  alpha is the frequency drift
+    over the observation relative to the mean frequency: a tone of mean
+    frequency r bins drifts by z = alpha r bins (reading)."""
+    if nalpha == 1:
+        return np.zeros(1)
+    d = 2.0 * alpha_max / (nalpha - 1)
+    return -alpha_max + d * np.arange(nalpha, dtype=np.float64)
+
+
+def td_resample(x: np.ndarray, alpha: float) -> np.ndarray:
+    """The series on a time axis along which a tone drifting by alpha (relative
+    to its mean frequency) has constant frequency (reading).
+
+    With u = n / N, v = u - 1/2, a tone of mean frequency rbar has phase
+    2 pi rbar (v + alpha v^2 / 2) + const; the new axis is tau = v + alpha v^2 / 2,
+    sampled at tau_m = m / N - 1/2, so sample m is x at
+        v_m = 2 tau_m / (1 + sqrt(1 + 2 alpha tau_m))    (the root with v -> tau as alpha -> 0),
+    position s_m = N (v_m + 1/2) samples, linearly interpolated between the two
+    neighbouring samples (zero outside the series).
+    """
+    x = np.asarray(x, dtype=np.float64)
+    N = x.shape[0]
+    tau = np.arange(N, dtype=np.float64) / N - 0.5
+    v = 2.0 * tau / (1.0 + np.sqrt(1.0 + 2.0 * alpha * tau))
+    spos = N * (v + 0.5)
+    i = np.floor(spos).astype(np.int64)
+    f = spos - i
+    xp = np.concatenate([x, [0.0]])  # x[N] = 0
+    ok = (i >= 0) & (i <= N - 1)
+    ic = np.clip(i, 0, N - 1)
+    return np.where(ok, xp[ic] * (1.0 - f) + xp[ic + 1] * f, 0.0)
+
+
+def td_harmonic_sum(P: np.ndarray, nh: int) -> np.ndarray:
+    """S_nh[i, k] = sum_{j=1}^{nh} P[i, k_j], k_j the rounding (half away from
+    zero) of j k / nh: resampling removes the drift of every harmonic at once,
+    so all harmonics of a trial lie in its own spectrum (reading)."""
+    nb = P.shape[1]
+    k = np.arange(nb, dtype=np.int64)
+    S = np.zeros_like(P, dtype=np.float64)
+    for j in range(1, nh + 1):
+        S += P[:, (2 * j * k + nh) // (2 * nh)]
+    return S
+
+
+def td_search(x, *, alpha_max: float, nalpha: int, sigma: float = 6.0, nharm_max: int = 16,
+              W: int = 1024, keep_sums: bool = False) -> SearchResult:
+    """The time-domain resampling search on one series, every step in FP64:
+    resample per trial (``td_resample``), real DFT (Sec. 4 step 2),
+    normalisation (``normalise``), powers, harmonic sums along each trial's
+    spectrum, thresholds and 3x3 local maxima over (trial, bin) as in
+    ``find_peaks``.  Candidates: iz is the trial, r = k / nharm the
+    fundamental's mean frequency, z = alpha r its drift over the
+    observation."""
+    alphas = td_alphas(alpha_max, nalpha)
+    rows = []
+    for a in alphas:
+        X = real_spectrum(td_resample(x, float(a)))
+        rows.append(np.abs(normalise(X, W)) ** 2)
+    P = np.array(rows)
+    nhs = harmonic_list(nharm_max)
+    thr = thresholds(sigma, nhs)
+    cands: List[Candidate] = []
+    sums = {}
+    for nh in nhs:
+        S = P if nh == 1 else td_harmonic_sum(P, nh)
+        if keep_sums:
+            sums[nh] = S
+        for iz, k in find_peaks(S, thr[nh]):
+            s = float(S[iz, k])
+            r = k / nh
+            cands.append(Candidate(k=int(k), iz=int(iz), nharm=nh, r=r, z=float(alphas[iz]) * r, power=s,
+                                   sigma=sigma_of(s, nh)))
+    return SearchResult(plane=P, candidates=cands, thresholds=thr, spectrum=None, zs=alphas, h=0, sums=sums)
