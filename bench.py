@@ -26,6 +26,8 @@ Prints one JSON line: the plain per-trial rate as ``value``, then
              the small configuration with every candidate refined;
   template_sweep  the plain rate at 51, 101, 201 and 401 templates;
   interbin   the plain rate with the half-bin plane (2 Nb columns);
+  time_domain  the time-domain resampling search on the same trials (201
+             acceleration trials, one long DFT each);
   precision  16 trials of 2^22 samples, 801 templates (z in [-400, 400],
              step 1): FP32 FFT correlation against the BF16 and FP16
              matrix-core correlators, with power error and candidate
@@ -346,6 +348,36 @@ def bench_interbin(fdas, bank, xs, pinned, steps: int = 8):
     return out
 
 
+TD_ALPHA_MAX, TD_NALPHA = 0.02, 201
+
+
+def bench_time_domain(fdas, xs, pinned, steps: int = 3):
+    """The time-domain resampling search (the other method of Sec. 1) on the
+    SKA-shaped trials: 201 acceleration trials |alpha| <= 0.02 (the drift
+    relative to the mean frequency; the injected pulsars have |z| / r up to
+    0.018), one 2^23-sample resampling and real DFT per trial, harmonic sums
+    along each trial's spectrum."""
+    import torch
+    plan = fdas.TdPlan(N, TD_ALPHA_MAX, TD_NALPHA, nharm_max=NHARM, sigma=SIGMA)
+    plan.search(xs[0], out=pinned)
+    torch.cuda.synchronize()
+    plan.enable_timing(True)
+    counts = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        _, n = plan.search(xs[i % len(xs)], out=pinned)
+        counts.append(int(n))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st, nt = plan.stage_times()
+    out = {"value": round(1.0 / dt, 3), "unit": "DM trials/s", "steps": steps, "ms_per_step": round(1e3 * dt, 3),
+           "trials": TD_NALPHA, "alpha_max": TD_ALPHA_MAX,
+           "spectra_ms": round(st["r2c"] / nt, 3), "harmonic_sum_ms": round(st["harmonic_sum"] / nt, 3),
+           "candidates_per_trial": counts}
+    plan.close()
+    return out
+
+
 C5_ZMAX, C5_DZ, C5_N = 400.0, 1.0, 1 << 22
 
 
@@ -570,6 +602,8 @@ def main():
     if extra:
         log("half-bin plane")
         out["interbin"] = bench_interbin(fdas, bank, xs, pinned)
+        log("time-domain resampling search")
+        out["time_domain"] = bench_time_domain(fdas, xs, pinned)
 
     if batch_host:
         bxs = [torch.from_numpy(x).to(dev) for x in batch_host]

@@ -167,6 +167,28 @@ fdas_status fdas_significance(double power, int32_t nharm, double *sigma);
  * thread-safe; calls on it are ordered on the stream they are given. */
 fdas_status fdas_plan(const fdas_bank *bank, int64_t nsamp, int32_t seg,
                       const fdas_opts *opts, fdas_plan_t **out);
+/* Time-domain resampling search (the other acceleration search named in
+ * Sec. 1): a plan of nalpha acceleration trials alpha_i = -alpha_max + i d,
+ * d = 2 alpha_max / (nalpha - 1) (alpha = 0 when nalpha is 1), where alpha
+ * is the frequency drift over the observation relative to the mean
+ * frequency (a tone of mean frequency r bins drifts by z = alpha r bins).
+ * fdas_search on this plan (float32 series input only) resamples the series
+ * for each trial onto the axis tau = v + alpha v^2 / 2 (v the time from the
+ * middle of the observation, in units of its length; linear interpolation,
+ * zero outside the series), takes its real DFT and block-median
+ * normalisation as in the template search, writes the powers as plane row i
+ * (plane_dev: float32[nalpha][Nb]), and sums harmonics along each row (all
+ * harmonics of a trial lie in its own spectrum) before the same thresholds
+ * and 3x3 peaks.  Candidates: iz is the trial, r = k / nharm the
+ * fundamental's mean frequency, z = alpha_iz r its drift.  One long DFT per
+ * trial: the expensive method the correlation search replaces.  opts:
+ * sigma, nharm_max, median_window and cand_capacity apply; correlator,
+ * interbin and refine_levels must be left at their defaults (INVAL
+ * otherwise).  INVAL unless 1 <= nalpha <= 4801 and 0 <= alpha_max <= 0.5.
+ * fdas_search_batch, fdas_refine and fdas_interp_power return INVAL on such a
+ * plan. */
+fdas_status fdas_td_plan(int64_t nsamp, double alpha_max, int32_t nalpha, const fdas_opts *opts,
+                         fdas_plan_t **out);
 int64_t fdas_plan_nbins(const fdas_plan_t *plan);
 int64_t fdas_plan_device_bytes(const fdas_plan_t *plan);
 void fdas_plan_destroy(fdas_plan_t *plan);

@@ -83,6 +83,7 @@ def load():
         "fdas_threshold": (_c_i32, [_c_dbl, _c_i32, P(_c_dbl)]),
         "fdas_significance": (_c_i32, [_c_dbl, _c_i32, P(_c_dbl)]),
         "fdas_plan": (_c_i32, [_c_vp, _c_i64, _c_i32, P(_Opts), P(_c_vp)]),
+        "fdas_td_plan": (_c_i32, [_c_i64, _c_dbl, _c_i32, P(_Opts), P(_c_vp)]),
         "fdas_plan_nbins": (_c_i64, [_c_vp]),
         "fdas_plan_device_bytes": (_c_i64, [_c_vp]),
         "fdas_plan_destroy": (None, [_c_vp]),
@@ -254,6 +255,7 @@ class Plan:
         _check(load().fdas_plan(bank.handle, int(nsamp), int(seg), ctypes.byref(o), ctypes.byref(h)))
         self._h = h
         self.bank = bank
+        self.rows = bank.nz
         self.nsamp, self.seg = int(nsamp), int(seg)
         self.opts = o
         self._buf = _CandBuffer()
@@ -281,8 +283,8 @@ class Plan:
         buf = out if out is not None else self._buf.get(max(cap, 1))
         if out is not None:
             cap = min(cap, out.shape[0])
-        if plane is not None and plane.numel() * plane.element_size() < 4 * self.bank.nz * self.plane_columns:
-            raise ValueError(f"plane must hold float32[{self.bank.nz}][{self.plane_columns}]")
+        if plane is not None and plane.numel() * plane.element_size() < 4 * self.rows * self.plane_columns:
+            raise ValueError(f"plane must hold float32[{self.rows}][{self.plane_columns}]")
         n = ctypes.c_int64()
         st = load().fdas_search(self._h, kind, ctypes.c_void_p(inp.data_ptr()),
                                 ctypes.c_void_p(plane.data_ptr() if plane is not None else 0),
@@ -370,6 +372,32 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+
+class TdPlan(Plan):
+    """Time-domain resampling search over nalpha acceleration trials
+    alpha_i = -alpha_max + i 2 alpha_max / (nalpha - 1); ``search`` takes a
+    float32 series and fills a float32[nalpha][nbins] plane."""
+
+    def __init__(self, nsamp: int, alpha_max: float, nalpha: int, **opts):
+        h = ctypes.c_void_p()
+        o = _opts(**opts)
+        _check(load().fdas_td_plan(int(nsamp), float(alpha_max), int(nalpha), ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self.bank = None
+        self.rows = int(nalpha)
+        self.nsamp, self.seg = int(nsamp), 0
+        self.alpha_max = float(alpha_max)
+        self.opts = o
+        self._buf = _CandBuffer()
+
+    @property
+    def alphas(self) -> np.ndarray:
+        if self.rows == 1:
+            return np.zeros(1)
+        d = 2.0 * self.alpha_max / (self.rows - 1)
+        return -self.alpha_max + d * np.arange(self.rows, dtype=np.float64)
 
 
 class Server:

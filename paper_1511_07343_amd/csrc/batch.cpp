@@ -83,6 +83,10 @@ extern "C" fdas_status fdas_search_batch(fdas_plan_t *plan, int32_t n, const flo
         set_error("plan is unusable after a device error");
         return FDAS_E_DEVICE;
     }
+    if (plan->td) {
+        set_error("batches need a template (FDAS) plan");
+        return FDAS_E_INVAL;
+    }
     int64_t total_cap = 0;
     for (int32_t i = 0; i < n; ++i) {
         if (!series_dev[i] || cap[i] < 0) {

@@ -45,6 +45,7 @@ struct Workspace {
     fdas_cand *final = nullptr;   // sorted public records
     uint32_t *h_count = nullptr;  // pinned host copy of the count
     float *series = nullptr;      // graph input: the trial is copied here first (batched path)
+    float *resampled = nullptr;   // time-domain search: the series resampled for one trial
 };
 
 }  // namespace fdas
@@ -66,6 +67,7 @@ struct fdas_plan_s {
     float2 *d_bank_half = nullptr;  // the same for the half-bin offsets (interbin)
     void *d_gemm = nullptr;    // template matrix of the matrix correlator
     int32_t corr = 0;          // FDAS_CORR_*
+    bool td = false;           // time-domain resampling search: nz trials alpha = -zmax + iz dz
     int num_cu = 256;          // compute units of the device (matrix correlator grid)
     std::array<fdas::Workspace, 2> ws{};
     std::array<hipStream_t, 2> aux{};
@@ -78,6 +80,7 @@ struct fdas_plan_s {
     std::array<hipEvent_t, FDAS_NSTAGES + 1> tev{};
     std::array<double, FDAS_NSTAGES> stage_ms{};
     int64_t timed = 0;
+    bool searched = false;  // a search has been enqueued
     // last search, for the inspection hook
     const float2 *last_X = nullptr;
     const double *last_med = nullptr;
@@ -90,6 +93,7 @@ extern thread_local std::string g_last_error;
 void set_error(const std::string &msg);
 fdas_status hip_fail(fdas_plan_s *plan, hipError_t e, const char *what);
 fdas_status validate_opts(const fdas_opts &o);
+void init_detection(fdas_plan_s *p, int64_t cells_plane);
 fdas_status check_nsamp(int64_t nsamp, int32_t seg, int32_t h);
 // Plane columns per frequency bin: 2 for a half-bin plane.
 inline int cols_per_bin(const fdas_plan_s *p) { return p->opts.interbin ? 2 : 1; }

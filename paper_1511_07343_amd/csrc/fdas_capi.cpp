@@ -91,7 +91,7 @@ Geometry make_geometry(int64_t nsamp, int32_t S, int32_t h, int32_t W, int cpb) 
     g.nb = nsamp / 2;
     g.ncol = g.nb * cpb;
     g.L = (S - 2 * h) & ~3;  // a multiple of 4: store chunks and code blocks never straddle two segments
-    g.nseg = (g.nb + g.L - 1) / g.L;
+    g.nseg = g.L > 0 ? (g.nb + g.L - 1) / g.L : 0;  // no segments without templates (time-domain search)
     g.nblk = (g.nb + W - 1) / W;
     return g;
 }
@@ -112,11 +112,54 @@ int64_t candidate_bytes(const fdas_plan_s *p, const Geometry &g) {
            int64_t(harmsum_scratch_bytes(p->nz, g.ncol, p->hit_cap, p->group_cap)) + 64 + (p->corr ? g.nb * 4 : 0);
 }
 
+// The time-domain resampling search on `st`: per trial, resample, real DFT,
+// block medians, normalised powers and codes into plane row iz; then the
+// harmonic sums along each row (izc < 0), peaks, candidates and their drift.
+// Timing stages: 0 the trials' spectra, 4 harmonic sums to sorted
+// candidates (the others stay empty).
+static fdas_status enqueue_td_search(fdas_plan_s *p, const Workspace &ws, const Geometry &g, int32_t in_kind,
+                                     const void *in_dev, float *plane, DevCand *dcands, uint32_t *dcount,
+                                     hipStream_t st, bool timed) {
+    if (in_kind != FDAS_IN_SERIES_F32) {
+        set_error("a time-domain plan searches float32 series only");
+        return FDAS_E_INVAL;
+    }
+    auto mark = [&](int i) -> hipError_t { return timed ? hipEventRecord(p->tev[size_t(i)], st) : hipSuccess; };
+    hipError_t e = mark(0);
+    const float *x = static_cast<const float *>(in_dev);
+    for (int32_t iz = 0; iz < p->nz && e == hipSuccess; ++iz) {
+        const double alpha = p->nz > 1 ? -p->zmax + p->dz * double(iz) : 0.0;
+        e = launch_td_resample(x, g.nsamp, alpha, ws.resampled, st);
+        if (e == hipSuccess) e = launch_r2c_packed(ws.resampled, g.nsamp, ws.Z, ws.work, st);
+        if (e == hipSuccess) e = launch_unpack_median(ws.Z, g.nsamp, ws.X, ws.med, p->W, st);
+        if (e == hipSuccess)
+            e = launch_td_power(ws.X, ws.med, p->W, g.nb, plane + int64_t(iz) * g.nb, ws.codes + int64_t(iz) * (g.nb / 2),
+                                p->code_inv, st);
+    }
+    if (e != hipSuccess) return hip_fail(p, e, "time-domain spectra");
+    for (int i = 1; i <= 4 && e == hipSuccess; ++i) e = mark(i);
+    if (e == hipSuccess) e = launch_zero_u32(dcount, 6, st);
+    if (e == hipSuccess)
+        e = launch_harmsum(plane, ws.codes, p->nz, g.nb, 0, -1, p->opts.nharm_max, p->thr_f, p->code_thr, ws.hits,
+                           p->hit_cap, p->group_cap, dcands, dcount, p->cand_cap, st);
+    if (e == hipSuccess)
+        e = launch_finish_candidates(dcands, dcount, p->cand_cap, ws.sort, p->nz, g.nb, 1, p->zmax, p->dz, ws.final, st);
+    if (e == hipSuccess) e = launch_td_drift(dcount, p->cand_cap, p->zmax, p->nz, ws.final, st);
+    for (int i = 5; i <= FDAS_NSTAGES && e == hipSuccess; ++i) e = mark(i);
+    if (e != hipSuccess) return hip_fail(p, e, "time-domain harmonic sums");
+    p->last_X = nullptr;  // no spectrum for refinement
+    p->last_med = nullptr;
+    p->last_nb = g.nb;
+    p->searched = true;
+    return FDAS_OK;
+}
+
 // Run the whole per-series path on `st`, writing the plane into `plane` and
 // candidates into the plan's device buffers (count at *dcount).
 fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &g, int32_t in_kind,
                            const void *in_dev, float *plane, DevCand *dcands, uint32_t *dcount,
                            hipStream_t st, bool timed) {
+    if (p->td) return enqueue_td_search(p, ws, g, in_kind, in_dev, plane, dcands, dcount, st, timed);
     hipError_t e;
     const float2 *X = nullptr;
     const double *med = nullptr;
@@ -178,6 +221,7 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
     p->last_X = X;
     p->last_med = med;
     p->last_nb = g.nb;
+    p->searched = true;
     return FDAS_OK;
 }
 
@@ -217,6 +261,7 @@ fdas_status copy_candidates(const fdas_plan_s *p, const Workspace &ws, fdas_cand
 
 static void free_workspace(Workspace &ws) {
     if (ws.Z) (void)hipFree(ws.Z);
+    if (ws.resampled) (void)hipFree(ws.resampled);
     if (ws.work) (void)hipFree(ws.work);
     if (ws.X) (void)hipFree(ws.X);
     if (ws.med) (void)hipFree(ws.med);
@@ -238,19 +283,22 @@ fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp) {
     const Geometry g = make_geometry(nsamp, p->S, p->h, p->W, cols_per_bin(p));
     const int64_t M = g.nb;
     hipError_t e;
-#define FDAS_ALLOC(ptr, bytes)                                                  \
-    e = hipMalloc(reinterpret_cast<void **>(&(ptr)), size_t(bytes));            \
-    if (e != hipSuccess) {                                                      \
-        (void)hipGetLastError(); /* a failed allocation must not fail later launches */ \
-        free_workspace(ws);                                                     \
-        set_error(std::string("hipMalloc ") + #ptr + ": " + hipGetErrorString(e)); \
-        return FDAS_E_NOMEM;                                                    \
-    }
+#define FDAS_ALLOC(ptr, bytes)                                                      \
+    do {                                                                            \
+        e = hipMalloc(reinterpret_cast<void **>(&(ptr)), size_t(bytes));            \
+        if (e != hipSuccess) {                                                      \
+            (void)hipGetLastError(); /* a failed allocation must not fail later launches */ \
+            free_workspace(ws);                                                     \
+            set_error(std::string("hipMalloc ") + #ptr + ": " + hipGetErrorString(e)); \
+            return FDAS_E_NOMEM;                                                    \
+        }                                                                           \
+    } while (0)
     FDAS_ALLOC(ws.Z, M * 8);
     FDAS_ALLOC(ws.work, M * 8);
     FDAS_ALLOC(ws.X, M * 8);
     FDAS_ALLOC(ws.med, g.nblk * 8);
-    FDAS_ALLOC(ws.seg, g.nseg * int64_t(p->S) * 8);
+    if (p->td) FDAS_ALLOC(ws.resampled, nsamp * 4);
+    else FDAS_ALLOC(ws.seg, g.nseg * int64_t(p->S) * 8);
     FDAS_ALLOC(ws.plane, int64_t(p->nz) * g.ncol * 4);
     FDAS_ALLOC(ws.codes, int64_t(p->nz) * (g.ncol / 2));
     if (p->corr != FDAS_CORR_FFT_F32) FDAS_ALLOC(ws.xl, g.nb * 4);
@@ -281,6 +329,39 @@ fdas_status collect(fdas_plan_s *p, Workspace &ws, fdas_cand *out, int64_t cap, 
     e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_fail(p, e, "search");
     return copy_candidates(p, ws, out, cap, ncands, st);
+}
+
+// Candidate capacities, thresholds and screening codes of a plan whose plane
+// has cells_plane cells.
+void init_detection(fdas_plan_s *p, int64_t cells_plane) {
+    const fdas_opts &o = p->opts;
+    p->cand_cap = uint32_t(o.cand_capacity > 0
+                               ? o.cand_capacity
+                               : std::min<int64_t>(int64_t(1) << 22, std::max<int64_t>(int64_t(1) << 16, cells_plane / 256)));
+    // Bins the harmonic-sum screen may pass on: 4 x the candidate capacity,
+    // and with the automatic capacity at least every bin of planes up to 2^24
+    // bins (dense low-threshold searches flag most blocks).
+    int64_t cells = int64_t(p->cand_cap) * 4;
+    if (o.cand_capacity <= 0) cells = std::max<int64_t>(cells, std::min<int64_t>(cells_plane, int64_t(1) << 24));
+    p->hit_cap = uint32_t(std::min<int64_t>(cells, int64_t(1) << 30));
+    p->group_cap = std::max<uint32_t>(p->hit_cap / 2, 1u);
+    int levels = 0;
+    while ((1 << levels) < o.nharm_max) ++levels;
+    for (int l = 0; l < 5; ++l) {
+        p->thr_d[l] = l <= levels ? threshold(o.sigma, 1 << l) : INFINITY;
+        p->thr_f[l] = float(p->thr_d[l]);
+    }
+    // Screening codes: delta = thr_max / 250, so a saturated code (255) clears
+    // every level.  An exact FP32 sum S >= thr_f has code sum >= S / delta up to
+    // a few roundings (< 2e-6 relative), hence >= floor(thr_f / delta (1 - 1e-5)).
+    // Thresholds near zero (very low sigma) make every cell pass the screen.
+    const double inv = 250.0 / double(p->thr_f[levels]);
+    const bool screen = inv > 0.0 && inv < 1e30;
+    p->code_inv = screen ? float(inv) : 1.f;
+    for (int l = 0; l < 5; ++l) {
+        const double t = double(p->thr_f[l]) * double(p->code_inv) * (1.0 - 1e-5);
+        p->code_thr[l] = l > levels ? 0x8000u : screen && t > 0.0 ? uint32_t(std::floor(t)) : 0u;
+    }
 }
 
 fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, const fdas_opts *opts,
@@ -326,34 +407,7 @@ fdas_status make_plan_core(const fdas_bank_s *bank, int64_t nsamp, int32_t seg, 
         set_error("the matrix correlators need h <= 271 (zmax <= 510)");
         return FDAS_E_INVAL;
     }
-    const int64_t cells_plane = int64_t(bank->nz) * (nsamp / 2) * cols_per_bin(p);
-    p->cand_cap = uint32_t(o.cand_capacity > 0
-                               ? o.cand_capacity
-                               : std::min<int64_t>(int64_t(1) << 22, std::max<int64_t>(int64_t(1) << 16, cells_plane / 256)));
-    // Bins the harmonic-sum screen may pass on: 4 x the candidate capacity,
-    // and with the automatic capacity at least every bin of planes up to 2^24
-    // bins (dense low-threshold searches flag most blocks).
-    int64_t cells = int64_t(p->cand_cap) * 4;
-    if (o.cand_capacity <= 0) cells = std::max<int64_t>(cells, std::min<int64_t>(cells_plane, int64_t(1) << 24));
-    p->hit_cap = uint32_t(std::min<int64_t>(cells, int64_t(1) << 30));
-    p->group_cap = std::max<uint32_t>(p->hit_cap / 2, 1u);
-    int levels = 0;
-    while ((1 << levels) < o.nharm_max) ++levels;
-    for (int l = 0; l < 5; ++l) {
-        p->thr_d[l] = l <= levels ? threshold(o.sigma, 1 << l) : INFINITY;
-        p->thr_f[l] = float(p->thr_d[l]);
-    }
-    // Screening codes: delta = thr_max / 250, so a saturated code (255) clears
-    // every level.  An exact FP32 sum S >= thr_f has code sum >= S / delta up to
-    // a few roundings (< 2e-6 relative), hence >= floor(thr_f / delta (1 - 1e-5)).
-    // Thresholds near zero (very low sigma) make every cell pass the screen.
-    const double inv = 250.0 / double(p->thr_f[levels]);
-    const bool screen = inv > 0.0 && inv < 1e30;
-    p->code_inv = screen ? float(inv) : 1.f;
-    for (int l = 0; l < 5; ++l) {
-        const double t = double(p->thr_f[l]) * double(p->code_inv) * (1.0 - 1e-5);
-        p->code_thr[l] = l > levels ? 0x8000u : screen && t > 0.0 ? uint32_t(std::floor(t)) : 0u;
-    }
+    init_detection(p, int64_t(bank->nz) * (nsamp / 2) * cols_per_bin(p));
     hipError_t e = hipGetDevice(&p->device);
     if (e != hipSuccess) {
         delete p;
@@ -539,12 +593,72 @@ fdas_status fdas_plan(const fdas_bank *bank, int64_t nsamp, int32_t seg, const f
     return FDAS_OK;
 }
 
+fdas_status fdas_td_plan(int64_t nsamp, double alpha_max, int32_t nalpha, const fdas_opts *opts,
+                         fdas_plan_t **out) {
+    if (!out) {
+        set_error("out is NULL");
+        return FDAS_E_INVAL;
+    }
+    *out = nullptr;
+    fdas_opts o;
+    if (opts) o = *opts; else fdas_default_opts(&o);
+    fdas_status st = validate_opts(o);
+    if (st != FDAS_OK) return st;
+    if (o.correlator != FDAS_CORR_FFT_F32 || o.interbin || o.refine_levels) {
+        set_error("a time-domain plan takes no correlator, half-bin plane or refinement options");
+        return FDAS_E_INVAL;
+    }
+    st = check_nsamp(nsamp, 0, 0);
+    if (st != FDAS_OK) return st;
+    if (nsamp / 2 < int64_t(o.median_window)) {
+        set_error("nsamp / 2 must be at least the median window");
+        return FDAS_E_INVAL;
+    }
+    if (nalpha < 1 || nalpha > 4801 || !(alpha_max >= 0.0 && alpha_max <= 0.5)) {
+        set_error("nalpha must be in [1, 4801] and alpha_max in [0, 0.5]");
+        return FDAS_E_INVAL;
+    }
+    auto *p = new (std::nothrow) fdas_plan_s;
+    if (!p) {
+        set_error("out of host memory");
+        return FDAS_E_NOMEM;
+    }
+    p->opts = o;
+    p->td = true;
+    p->zmax = alpha_max;
+    p->dz = nalpha > 1 ? 2.0 * alpha_max / double(nalpha - 1) : 0.0;
+    p->nz = nalpha;
+    p->h = 0;
+    p->izc = -1;
+    p->S = 0;
+    p->log2s = 0;
+    p->W = o.median_window;
+    p->nsamp = nsamp;
+    p->tpb = 1;
+    p->corr = FDAS_CORR_FFT_F32;
+    init_detection(p, int64_t(nalpha) * (nsamp / 2));
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        delete p;
+        set_error(std::string("no HIP device: ") + hipGetErrorString(e));
+        return FDAS_E_DEVICE;
+    }
+    st = alloc_workspace(p, p->ws[0], nsamp);
+    if (st != FDAS_OK) {
+        fdas_plan_destroy(p);
+        return st;
+    }
+    *out = p;
+    return FDAS_OK;
+}
+
 int64_t fdas_plan_nbins(const fdas_plan_t *plan) { return plan ? plan->nsamp / 2 : 0; }
 
 int64_t fdas_plan_device_bytes(const fdas_plan_t *plan) {
     if (!plan) return 0;
-    int64_t b = plan->corr == FDAS_CORR_FFT_F32 ? int64_t(plan->nz) * plan->S * 8 * cols_per_bin(plan)
-                                                : int64_t(gemm_bank_bytes(plan->nz, plan->h));
+    int64_t b = plan->td ? 0
+                : plan->corr == FDAS_CORR_FFT_F32 ? int64_t(plan->nz) * plan->S * 8 * cols_per_bin(plan)
+                                                  : int64_t(gemm_bank_bytes(plan->nz, plan->h));
     for (const Workspace &ws : plan->ws) {
         if (ws.nsamp) {
             const Geometry g = make_geometry(ws.nsamp, plan->S, plan->h, plan->W, cols_per_bin(plan));
@@ -643,7 +757,7 @@ fdas_status fdas_plan_search_counts(const fdas_plan_t *plan, int64_t *out3) {
         return FDAS_E_INVAL;
     }
     const uint32_t *c = plan->ws[0].h_count;
-    if (!c || !plan->last_X) {
+    if (!c || !plan->searched) {
         set_error("no search has run on this plan");
         return FDAS_E_INVAL;
     }
@@ -680,6 +794,10 @@ fdas_status fdas_plan_fetch_spectrum(fdas_plan_t *plan, void *spectrum_dev, doub
 
 fdas_status fdas_interp_power(fdas_plan_t *plan, int64_t n, const double *r, const double *z, const int32_t *nharm,
                               double *power_out, void *hip_stream) {
+    if (plan && plan->td) {
+        set_error("interpolation needs a template (FDAS) plan");
+        return FDAS_E_INVAL;
+    }
     if (!plan || !plan->last_X) {
         set_error("no search has run on this plan");
         return FDAS_E_INVAL;
@@ -718,6 +836,10 @@ fdas_status fdas_interp_power(fdas_plan_t *plan, int64_t n, const double *r, con
 }
 
 fdas_status fdas_refine(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t levels, void *hip_stream) {
+    if (plan && plan->td) {
+        set_error("refinement needs a template (FDAS) plan");
+        return FDAS_E_INVAL;
+    }
     if (!plan || !plan->last_X) {
         set_error("no search has run on this plan");
         return FDAS_E_INVAL;

@@ -356,7 +356,10 @@ struct Thr {
 //   row    r_j(iz) = izc + sgn(d) floor((|d| j + 8) / 16),  d = iz - izc,
 // the rounding (half away from zero) of k j/16 and d j/16, i.e. of
 // k j'/nh and d j'/nh for the j'-th harmonic of an nh-harmonic sum.
+// izc < 0: every harmonic lies in the cell's own row (the time-domain search,
+// whose resampling removes the drift of all harmonics), row izc + d.
 __device__ __forceinline__ int frac_row(int izc, int d, int j) {
+    if (izc < 0) return izc + d;
     const int ad = d < 0 ? -d : d;
     const int off = (ad * j + 8) >> 4;
     return d < 0 ? izc - off : izc + off;

@@ -90,7 +90,8 @@ hipError_t launch_corr_gemm(const uint32_t *xl, int64_t nb, int h, const void *b
 // count[0]; count[1] counts bins reaching a threshold, count[4] and count[5]
 // listed bins and groups; count[2] is set to 1 if a list overflowed (the
 // candidates are then incomplete).  nb (plane columns) must be a multiple of
-// 32, nz at most 65535.  split > 0 marks a half-bin plane stored as two
+// 32, nz at most 65535; izc < 0 sums every harmonic in the cell's own row.
+// split > 0 marks a half-bin plane stored as two
 // halves per row: column c (in half bins) at c / 2 for even c and at
 // split + c / 2 for odd c.
 size_t harmsum_scratch_bytes(int nz, int64_t nb, uint32_t cell_cap, uint32_t group_cap);
@@ -107,6 +108,17 @@ hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int6
 size_t cand_sort_scratch_bytes(uint32_t cap);
 hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch, int nz,
                                     int64_t nb, int cpb, double zmax, double dz, fdas_cand *out, hipStream_t st);
+
+// Time-domain resampling search: y = x resampled for drift alpha (relative
+// to the mean frequency; linear interpolation, FP64 positions); normalised
+// powers |X|^2 ln2 / m(k) of one trial into a plane row with their 2-bin
+// codes (nb % 4 == 0); candidate drift z = alpha(iz) r with alpha(iz) =
+// -alpha_max + iz 2 alpha_max / (nalpha - 1).
+hipError_t launch_td_resample(const float *x, int64_t nsamp, double alpha, float *y, hipStream_t st);
+hipError_t launch_td_power(const float2 *X, const double *med, int W, int64_t nb, float *row, uint8_t *qrow,
+                           float code_inv, hipStream_t st);
+hipError_t launch_td_drift(const uint32_t *count, uint32_t cap, double alpha_max, int nalpha, fdas_cand *cands,
+                           hipStream_t st);
 
 // Candidate refinement (Fourier interpolation off the grid): for each of the
 // first min(*count, cap) public records, a pattern search over the
