@@ -26,6 +26,8 @@ segmentation, no blocking:
 9. ``td_search``       the time-domain resampling search the paper names as
                         the other method (Sec. 1): resample per acceleration,
                         one long DFT each, harmonic sums along each spectrum.
+10. ``dedisperse``     the de-dispersion that produces the series (Sec. 1:
+                        one series per dispersion-measure trial).
 
 Parity pins for each function live in tests/test_oracle_*.py.
 """
@@ -75,6 +77,9 @@ __all__ = [
     "td_resample",
     "td_harmonic_sum",
     "td_search",
+    "KDM",
+    "dm_delays",
+    "dedisperse",
 ]
 
 LN2 = math.log(2.0)
@@ -675,3 +680,36 @@ def td_search(x, *, alpha_max: float, nalpha: int, sigma: float = 6.0, nharm_max
             cands.append(Candidate(k=int(k), iz=int(iz), nharm=nh, r=r, z=float(alphas[iz]) * r, power=s,
                                    sigma=sigma_of(s, nh)))
     return SearchResult(plane=P, candidates=cands, thresholds=thr, spectrum=None, zs=alphas, h=0, sums=sums)
+
+
+# --------------------------------------------------------------------------
+# 10. De-dispersion (Sec. 1: the step before the search, one series per DM)
+# --------------------------------------------------------------------------
+KDM = 4.148808e3  # dispersion constant, s MHz^2 pc^-1 cm^3 (cold-plasma delay)
+
+
+def dm_delays(nchan: int, f_top: float, foff: float, tsamp: float, dms) -> np.ndarray:
+    """Integer sample delays d[i, c] = floor(KDM DM_i (f_c^-2 - f_top^-2) / tsamp + 1/2)
+    of channel c (frequency f_c = f_top - c foff MHz) relative to the top of the
+    band, for each DM (pc cm^-3): the cold-plasma dispersion delay rounded to
+    the nearest sample (reading: the paper only names de-dispersion)."""
+    f = f_top - foff * np.arange(nchan, dtype=np.float64)
+    dms = np.asarray(dms, dtype=np.float64)
+    raw = KDM * dms[:, None] * (1.0 / (f[None, :] * f[None, :]) - 1.0 / (f_top * f_top)) / tsamp
+    return np.floor(raw + 0.5).astype(np.int64)
+
+
+def dedisperse(fil: np.ndarray, f_top: float, foff: float, tsamp: float, dms, nout: int) -> np.ndarray:
+    """y[i, t] = sum_c fil[c, t + d[i, c]] for t < nout: the channels of a
+    channel-major filterbank (nchan x nsamp samples, 8-bit) shifted by their
+    delays and added, in exact integer arithmetic (returned as float64)."""
+    fil = np.asarray(fil)
+    nchan, nsamp = fil.shape
+    d = dm_delays(nchan, f_top, foff, tsamp, dms)
+    if nout > nsamp - int(d.max(initial=0)):
+        raise ValueError("nout exceeds the samples every channel can supply")
+    out = np.zeros((d.shape[0], nout), dtype=np.int64)
+    for i in range(d.shape[0]):
+        for c in range(nchan):
+            out[i] += fil[c, d[i, c]:d[i, c] + nout].astype(np.int64)
+    return out.astype(np.float64)

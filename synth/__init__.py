@@ -38,6 +38,8 @@ __all__ = [
     "single_tone_series",
     "draw_pulsars",
     "ska_trial",
+    "Dispersed",
+    "make_filterbank",
     "batch_trials",
     "served_trace",
     "precision_trials",
@@ -173,3 +175,41 @@ def served_trace(count: int = 6000, seed: int = 4, duration_s: float = 530.0,
 def served_request(entry) -> Trial:
     """The series of one request from ``served_trace``."""
     return _trial_with_random_pulsars(entry["nsamp"], entry["seed"], 1 if entry["has_pulsar"] else 0)
+
+
+@dataclass(frozen=True)
+class Dispersed:
+    """A periodic pulsar injected into a filterbank: pulses of Gaussian shape
+    (width in seconds) every ``period`` seconds, dispersed by ``dm``
+    (pc cm^-3) with the cold-plasma delay of each channel."""
+
+    period: float
+    dm: float
+    width: float
+    amp: float  # peak height in the 8-bit units of the noise (sigma 16)
+    phase0: float = 0.0  # arrival time of the first pulse at the top of the band, s
+
+
+# cold-plasma dispersion delay constant, s MHz^2 pc^-1 cm^3 (signal model of the injection)
+_DISPERSION_S = 4.148808e3
+
+
+def make_filterbank(nchan: int, nsamp: int, f_top: float, foff: float, tsamp: float, seed: int,
+                    pulsars=(), mean: float = 128.0, sigma: float = 16.0) -> np.ndarray:
+    """Channel-major 8-bit filterbank (nchan x nsamp): Gaussian noise of the
+    given mean and sigma, plus dispersed periodic pulses (continuous delays),
+    rounded to the nearest integer and clipped to [0, 255].  Channel c has
+    frequency f_top - c foff MHz."""
+    rng = np.random.default_rng(seed)
+    fil = np.empty((nchan, nsamp), dtype=np.uint8)
+    t = np.arange(nsamp, dtype=np.float64) * tsamp
+    for c in range(nchan):
+        row = mean + sigma * rng.standard_normal(nsamp)
+        f = f_top - foff * c
+        for p in pulsars:
+            delay = _DISPERSION_S * p.dm * (1.0 / (f * f) - 1.0 / (f_top * f_top))
+            ph = (t - p.phase0 - delay) / p.period
+            dt = (ph - np.round(ph)) * p.period  # time from the nearest pulse
+            row += p.amp * np.exp(-0.5 * (dt / p.width) ** 2)
+        fil[c] = np.clip(np.rint(row), 0, 255).astype(np.uint8)
+    return fil
