@@ -283,6 +283,23 @@ fdas_status fdas_refine(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t 
 fdas_status fdas_plan_fetch_spectrum(fdas_plan_t *plan, void *spectrum_dev, double *medians_dev,
                                      void *hip_stream);
 
+/* De-dispersion, the step that produces the series (Sec. 1: one series per
+ * dispersion-measure trial, ~6000 for an SKA beam).  fil_dev: device
+ * channel-major 8-bit filterbank, nchan rows of nsamp samples, channel c at
+ * f_top - c foff MHz (foff >= 0: descending frequencies).  Trial i shifts
+ * channel c by d[i][c] = floor(k DM_i (f_c^-2 - f_top^-2) / tsamp + 1/2) samples
+ * (k = 4.148808e3 s MHz^2 pc^-1 cm^3, the cold-plasma dispersion delay,
+ * rounded to the nearest sample; tsamp in s; dms: host array of ndm values
+ * >= 0, pc cm^-3) and writes out_dev[i][t] = sum_c fil[c][t + d[i][c]] for
+ * t < nout (device float32[ndm][nout]; exact integer sums).  INVAL unless
+ * nout <= nsamp - max d, 1 <= nchan, ndm <= 65536 and every frequency is
+ * positive.  Synchronous; allocates 4 ndm nchan bytes of device memory for
+ * the call.  The output rows are series for fdas_search (nout a power of
+ * two) or fdas_search_batch. */
+fdas_status fdas_dedisperse(const uint8_t *fil_dev, int32_t nchan, int64_t nsamp, double f_top, double foff,
+                            double tsamp, const double *dms, int32_t ndm, int64_t nout, float *out_dev,
+                            void *hip_stream);
+
 /* Batched unnormalised complex DFT of length 2^log2n (6 <= log2n <= 13) on
  * device c64 data, in-place allowed: out[b][f] = sum_n in[b][n] e^{-+2 pi i n f / 2^log2n},
  * sign - for inverse = 0, + for inverse = 1.  The workgroup DFT of the hot path. */

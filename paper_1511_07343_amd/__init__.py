@@ -15,8 +15,9 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 __all__ = [
-    "FdasError", "load", "lib_path", "CAND_DTYPE", "Bank", "Plan", "Server",
-    "make_templates", "autotune", "threshold", "significance", "dft_c64", "pinned_candidates", "IN_SERIES", "IN_SPECTRUM",
+    "FdasError", "load", "lib_path", "CAND_DTYPE", "Bank", "Plan", "TdPlan", "Server",
+    "make_templates", "autotune", "threshold", "significance", "dft_c64", "dedisperse", "pinned_candidates",
+    "IN_SERIES", "IN_SPECTRUM",
     "IN_SPECTRUM_NORMALISED",
 ]
 
@@ -84,6 +85,8 @@ def load():
         "fdas_significance": (_c_i32, [_c_dbl, _c_i32, P(_c_dbl)]),
         "fdas_plan": (_c_i32, [_c_vp, _c_i64, _c_i32, P(_Opts), P(_c_vp)]),
         "fdas_td_plan": (_c_i32, [_c_i64, _c_dbl, _c_i32, P(_Opts), P(_c_vp)]),
+        "fdas_dedisperse": (_c_i32, [_c_vp, _c_i32, _c_i64, _c_dbl, _c_dbl, _c_dbl, P(_c_dbl), _c_i32, _c_i64,
+                                     _c_vp, _c_vp]),
         "fdas_plan_nbins": (_c_i64, [_c_vp]),
         "fdas_plan_device_bytes": (_c_i64, [_c_vp]),
         "fdas_plan_destroy": (None, [_c_vp]),
@@ -475,4 +478,22 @@ def dft_c64(x, inverse: bool = False, out=None, stream=None):
     batch = x.numel() // n
     _check(load().fdas_dft_c64(log2n, int(inverse), batch, ctypes.c_void_p(x.data_ptr()),
                                ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+    return out
+
+
+def dedisperse(fil, f_top: float, foff: float, tsamp: float, dms, nout: int, out=None, stream=None):
+    """De-disperse a channel-major uint8 CUDA filterbank (nchan x nsamp, channel
+    c at f_top - c foff MHz) for each DM: float32 CUDA tensor [ndm, nout]."""
+    import torch
+    if fil.dtype != torch.uint8 or not fil.is_cuda or fil.dim() != 2:
+        raise TypeError("dedisperse needs a 2-d uint8 CUDA tensor (channels x samples)")
+    fil = fil.contiguous()
+    dms = np.ascontiguousarray(dms, dtype=np.float64)
+    if out is None:
+        out = torch.empty((dms.size, int(nout)), dtype=torch.float32, device=fil.device)
+    elif out.dtype != torch.float32 or out.numel() < dms.size * int(nout) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous float32 tensor of ndm x nout")
+    _check(load().fdas_dedisperse(ctypes.c_void_p(fil.data_ptr()), fil.shape[0], fil.shape[1], float(f_top),
+                                  float(foff), float(tsamp), dms.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  dms.size, int(nout), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out

@@ -33,7 +33,7 @@ CXX_FLAGS = [
     "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROCM, "include"), "-I", os.path.join(ROOT, "include"),
 ]
 
-HIP_SOURCES = ["kernels.hip", "candidates.hip", "gemm_corr.hip", "refine.hip", "tdas.hip"]
+HIP_SOURCES = ["kernels.hip", "candidates.hip", "gemm_corr.hip", "refine.hip", "tdas.hip", "dedisp.hip"]
 CXX_SOURCES = ["host_math.cpp", "fdas_capi.cpp", "batch.cpp", "server.cpp", "autotune.cpp"]
 
 

@@ -881,6 +881,59 @@ fdas_status fdas_refine(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t 
     return FDAS_OK;
 }
 
+fdas_status fdas_dedisperse(const uint8_t *fil_dev, int32_t nchan, int64_t nsamp, double f_top, double foff,
+                            double tsamp, const double *dms, int32_t ndm, int64_t nout, float *out_dev,
+                            void *hip_stream) {
+    if (!fil_dev || !out_dev || !dms || nchan < 1 || nchan > 65536 || ndm < 1 || ndm > 65536 || nsamp < 1 ||
+        nout < 1 || !(tsamp > 0.0) || !(foff >= 0.0) || !(f_top - foff * double(nchan - 1) > 0.0) ||
+        !std::isfinite(f_top)) {
+        set_error("fdas_dedisperse: bad filterbank, frequency, sampling or DM arguments");
+        return FDAS_E_INVAL;
+    }
+    // delays d[i][c] = floor(KDM DM_i (f_c^-2 - f_top^-2) / tsamp + 1/2), FP64
+    constexpr double kKdm = 4.148808e3;  // s MHz^2 pc^-1 cm^3
+    std::vector<int32_t> d(size_t(ndm) * size_t(nchan));
+    int64_t dmax = 0;
+    for (int32_t i = 0; i < ndm; ++i) {
+        if (!(dms[i] >= 0.0) || !std::isfinite(dms[i])) {
+            set_error("fdas_dedisperse: DMs must be finite and >= 0");
+            return FDAS_E_INVAL;
+        }
+        for (int32_t c = 0; c < nchan; ++c) {
+            const double f = f_top - foff * double(c);
+            const double raw = kKdm * dms[i] * (1.0 / (f * f) - 1.0 / (f_top * f_top)) / tsamp;
+            const double v = std::floor(raw + 0.5);
+            if (!(v < double(nsamp))) {
+                set_error("fdas_dedisperse: a delay exceeds the filterbank");
+                return FDAS_E_INVAL;
+            }
+            d[size_t(i) * nchan + c] = int32_t(v);
+            dmax = std::max<int64_t>(dmax, int64_t(v));
+        }
+    }
+    if (nout > nsamp - dmax) {
+        set_error("fdas_dedisperse: nout exceeds nsamp minus the largest delay");
+        return FDAS_E_INVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    int32_t *dd = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&dd), d.size() * sizeof(int32_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("fdas_dedisperse: device allocation failed");
+        return FDAS_E_NOMEM;
+    }
+    if ((e = hipMemcpyAsync(dd, d.data(), d.size() * sizeof(int32_t), hipMemcpyHostToDevice, st)) == hipSuccess &&
+        (e = launch_dedisperse(fil_dev, nchan, nsamp, dd, ndm, nout, out_dev, st)) == hipSuccess)
+        e = hipStreamSynchronize(st);
+    const hipError_t ef = hipFree(dd);
+    if (e != hipSuccess || ef != hipSuccess) {
+        set_error(std::string("fdas_dedisperse: ") + hipGetErrorString(e != hipSuccess ? e : ef));
+        return FDAS_E_DEVICE;
+    }
+    return FDAS_OK;
+}
+
 fdas_status fdas_dft_c64(int32_t log2n, int32_t inverse, int64_t batch, const void *in_dev, void *out_dev,
                          void *hip_stream) {
     if (log2n < 6 || log2n > 13 || batch < 0 || batch > 0x7fffffff || (batch > 0 && (!in_dev || !out_dev))) {

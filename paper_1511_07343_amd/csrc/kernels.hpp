@@ -109,6 +109,12 @@ size_t cand_sort_scratch_bytes(uint32_t cap);
 hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch, int nz,
                                     int64_t nb, int cpb, double zmax, double dz, fdas_cand *out, hipStream_t st);
 
+// De-dispersion: out[i][t] = sum_c fil[c][t + delays[i][c]] for t < nout
+// (channel-major 8-bit filterbank, nchan x nsamp; exact integer sums stored
+// as float32).  Every t + delay must lie below nsamp (the caller checks).
+hipError_t launch_dedisperse(const uint8_t *fil, int nchan, int64_t nsamp, const int32_t *delays, int ndm,
+                             int64_t nout, float *out, hipStream_t st);
+
 // Time-domain resampling search: y = x resampled for drift alpha (relative
 // to the mean frequency; linear interpolation, FP64 positions); normalised
 // powers |X|^2 ln2 / m(k) of one trial into a plane row with their 2-bin
