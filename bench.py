@@ -28,6 +28,8 @@ Prints one JSON line: the plain per-trial rate as ``value``, then
   interbin   the plain rate with the half-bin plane (2 Nb columns);
   time_domain  the time-domain resampling search on the same trials (201
              acceleration trials, one long DFT each);
+  dedisperse the de-dispersion front end: 256 DM trials of a 64-channel
+             8-bit filterbank into 2^23-sample series;
   precision  16 trials of 2^22 samples, 801 templates (z in [-400, 400],
              step 1): FP32 FFT correlation against the BF16 and FP16
              matrix-core correlators, with power error and candidate
@@ -348,6 +350,40 @@ def bench_interbin(fdas, bank, xs, pinned, steps: int = 8):
     return out
 
 
+DD_NCHAN, DD_FTOP, DD_FOFF, DD_TSAMP, DD_NDM, DD_DMMAX = 64, 1500.0, 4.0, 64e-6, 256, 500.0
+
+
+def bench_dedisperse(fdas, steps: int = 3):
+    """De-dispersion front end at the SKA series length: a 64-channel 8-bit
+    filterbank (1500 MHz top, 4 MHz channels, 64 us samples: 2^23 output
+    samples is 537 s), 256 DM trials over [0, 500] pc cm^-3.  The filterbank
+    is seeded uniform noise drawn on the device (a timing input; the tests
+    check the sums bit for bit on synthetic filterbanks)."""
+    import numpy as np
+    import torch
+    dms = np.linspace(0.0, DD_DMMAX, DD_NDM)
+    f_bot = DD_FTOP - DD_FOFF * (DD_NCHAN - 1)
+    dmax = int(np.floor(4.148808e3 * DD_DMMAX * (1 / f_bot ** 2 - 1 / DD_FTOP ** 2) / DD_TSAMP + 0.5))
+    nsamp = N + dmax
+    g = torch.Generator(device="cuda")
+    g.manual_seed(6)
+    fil = torch.randint(0, 256, (DD_NCHAN, nsamp), dtype=torch.uint8, device="cuda", generator=g)
+    out = torch.empty((DD_NDM, N), dtype=torch.float32, device="cuda")
+    fdas.dedisperse(fil, DD_FTOP, DD_FOFF, DD_TSAMP, dms, N, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fdas.dedisperse(fil, DD_FTOP, DD_FOFF, DD_TSAMP, dms, N, out=out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    written = DD_NDM * N * 4
+    return {"value": round(DD_NDM / dt, 1), "unit": "DM trials/s", "dm_trials": DD_NDM, "channels": DD_NCHAN,
+            "nsamp_out": N, "max_delay": dmax, "ms_per_call": round(1e3 * dt, 3),
+            "series_written_GBs": round(written / dt / 1e9, 1),
+            "channel_bytes_added_per_s": round(DD_NDM * DD_NCHAN * N / dt, 1),
+            "data": "seeded uniform 8-bit noise drawn on the device (torch generator, seed 6)"}
+
+
 TD_ALPHA_MAX, TD_NALPHA = 0.02, 201
 
 
@@ -604,6 +640,8 @@ def main():
         out["interbin"] = bench_interbin(fdas, bank, xs, pinned)
         log("time-domain resampling search")
         out["time_domain"] = bench_time_domain(fdas, xs, pinned)
+        log("de-dispersion front end")
+        out["dedisperse"] = bench_dedisperse(fdas)
 
     if batch_host:
         bxs = [torch.from_numpy(x).to(dev) for x in batch_host]

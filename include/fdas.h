@@ -285,7 +285,8 @@ fdas_status fdas_plan_fetch_spectrum(fdas_plan_t *plan, void *spectrum_dev, doub
 
 /* De-dispersion, the step that produces the series (Sec. 1: one series per
  * dispersion-measure trial, ~6000 for an SKA beam).  fil_dev: device
- * channel-major 8-bit filterbank, nchan rows of nsamp samples, channel c at
+ * channel-major 8-bit filterbank (4-byte aligned), nchan rows of nsamp
+ * samples, channel c at
  * f_top - c foff MHz (foff >= 0: descending frequencies).  Trial i shifts
  * channel c by d[i][c] = floor(k DM_i (f_c^-2 - f_top^-2) / tsamp + 1/2) samples
  * (k = 4.148808e3 s MHz^2 pc^-1 cm^3, the cold-plasma dispersion delay,

@@ -884,7 +884,8 @@ fdas_status fdas_refine(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t 
 fdas_status fdas_dedisperse(const uint8_t *fil_dev, int32_t nchan, int64_t nsamp, double f_top, double foff,
                             double tsamp, const double *dms, int32_t ndm, int64_t nout, float *out_dev,
                             void *hip_stream) {
-    if (!fil_dev || !out_dev || !dms || nchan < 1 || nchan > 65536 || ndm < 1 || ndm > 65536 || nsamp < 1 ||
+    if (!fil_dev || !out_dev || !dms || (reinterpret_cast<uintptr_t>(fil_dev) & 3u) != 0 || nchan < 1 ||
+        nchan > 65536 || ndm < 1 || ndm > 65536 || nsamp < 1 ||
         nout < 1 || !(tsamp > 0.0) || !(foff >= 0.0) || !(f_top - foff * double(nchan - 1) > 0.0) ||
         !std::isfinite(f_top)) {
         set_error("fdas_dedisperse: bad filterbank, frequency, sampling or DM arguments");
