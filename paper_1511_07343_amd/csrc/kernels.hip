@@ -72,6 +72,13 @@ __global__ __launch_bounds__(fft_threads(LOG2M)) void k_r2c_small(const float2 *
     for (int m = 0; m < Sh::R; ++m) Z[t + Sh::NT * m] = v[m];
 }
 
+// Workgroup i of n: with n a multiple of the 8 XCDs, the index that puts a
+// contiguous range of n / 8 columns (or rows) on each XCD, so that the
+// neighbours whose strided accesses share cache lines share its L2.
+__device__ __forceinline__ int64_t xcd_spread(int64_t i, int64_t n) {
+    return (n % kXcds == 0) ? (i % kXcds) * (n / kXcds) + i / kXcds : i;
+}
+
 // Four-step M = M1 * M2 (n = n2 + M2 n1, k = k1 + M1 k2).
 // Pass A, one workgroup per column n2: DFT over n1, times exp(-2 pi i n2 k1 / M),
 // stored at work[n2 + M2 k1].
@@ -84,7 +91,7 @@ __global__ __launch_bounds__(fft_threads(LOG2M1)) void k_r2c_cols(const float2 *
     const int t = threadIdx.x;
     const int64_t M2 = int64_t(1) << log2m2;
     const int64_t M = M2 << LOG2M1;
-    const int64_t n2 = blockIdx.x;
+    const int64_t n2 = xcd_spread(blockIdx.x, gridDim.x);  // adjacent columns share lines
     Twiddles<Sh, -1> tw;
     tw.init(t);
     float2 v[Sh::R];
@@ -110,7 +117,7 @@ __global__ __launch_bounds__(fft_threads(LOG2M2)) void k_r2c_rows(const float2 *
     using Sh = FftShape<LOG2M2, fft_threads(LOG2M2)>;
     __shared__ float2 lds[Sh::LDS_FLOAT2];
     const int t = threadIdx.x;
-    const int64_t k1 = blockIdx.x;
+    const int64_t k1 = xcd_spread(blockIdx.x, gridDim.x);  // adjacent rows' outputs share lines
     Twiddles<Sh, -1> tw;
     tw.init(t);
     float2 v[Sh::R];
