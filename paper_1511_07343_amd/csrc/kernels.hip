@@ -129,81 +129,135 @@ __global__ __launch_bounds__(fft_threads(LOG2M2)) void k_r2c_rows(const float2 *
 }
 
 // ------------------------------------------------------ medians of |X|^2
-// Ascending bitonic sort of W (power of two) floats in LDS.  Strides are
-// powers of two, so pair indices are formed with shifts and masks.
-__device__ void bitonic_sort_lds(float *s, int W) {
-    const int t = threadIdx.x, nt = blockDim.x;
-    for (int size = 2; size <= W; size <<= 1) {
-        for (int lg = __ffs(size) - 2; lg >= 0; --lg) {
-            const int stride = 1 << lg;
-            __syncthreads();
-            for (int i = t; i < (W >> 1); i += nt) {
-                const int lo = ((i >> lg) << (lg + 1)) | (i & (stride - 1));  // 2 stride (i / stride) + i % stride
-                const int hi = lo + stride;
-                const bool asc = (lo & size) == 0;
-                const float a = s[lo], b = s[hi];
-                if ((a > b) == asc) {
-                    s[lo] = b;
-                    s[hi] = a;
-                }
-            }
+// Order statistics of W powers in LDS by radix selection on their bit
+// patterns (non-negative floats and +inf order as their unsigned bits): four
+// passes of 8 bits, each a 256-bucket histogram and a scan that finds the
+// bucket holding the wanted rank.  The result is the exact rank-r value, as
+// a sort would give.
+constexpr int kMedThreads = 256;
+
+static_assert(kMedThreads == 256, "one histogram bucket per thread");
+
+struct SelectScratch {
+    uint32_t hist[256];
+    uint32_t wave_tot[kMedThreads / 64];
+    uint32_t pick[2];  // bucket, rank within it
+};
+
+__device__ uint32_t select_rank(const uint32_t *u, int n, uint32_t rank, SelectScratch &sc) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t prefix = 0, mask = 0;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        sc.hist[t] = 0;  // kMedThreads == 256 buckets
+        __syncthreads();
+        for (int i = t; i < n; i += kMedThreads) {
+            const uint32_t key = u[i];
+            if ((key & mask) == prefix) atomicAdd(&sc.hist[(key >> shift) & 255u], 1u);
         }
+        __syncthreads();
+        // inclusive scan of the 256 counts: within each wave, then across the 4
+        const uint32_t c = sc.hist[t];
+        uint32_t incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o);
+            if (lane >= o) incl += y;
+        }
+        if (lane == 63) sc.wave_tot[wave] = incl;
+        __syncthreads();
+        for (int w = 0; w < wave; ++w) incl += sc.wave_tot[w];
+        const uint32_t excl = incl - c;
+        if (excl <= rank && rank < incl) {
+            sc.pick[0] = uint32_t(t);
+            sc.pick[1] = rank - excl;
+        }
+        __syncthreads();
+        prefix |= sc.pick[0] << shift;
+        mask |= 255u << shift;
+        rank = sc.pick[1];
+        __syncthreads();  // pick and hist are rewritten by the next pass
+    }
+    return prefix;
+}
+
+// Median of the n valid keys (mean of the middle pair for even n), in FP64:
+// rank (n - 1) / 2 by selection; for even n the next rank is that value again
+// when it occurs more than once up to it, else the smallest larger key.
+__device__ double median_select(const uint32_t *u, int n, SelectScratch &sc) {
+    const uint32_t r1 = uint32_t(n - 1) >> 1;
+    const uint32_t v1 = select_rank(u, n, r1, sc);
+    if (n & 1) return double(__uint_as_float(v1));
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t le = 0, above = 0xffffffffu;
+    for (int i = t; i < n; i += kMedThreads) {
+        const uint32_t key = u[i];
+        le += key <= v1 ? 1u : 0u;
+        if (key > v1) above = min(above, key);
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        le += __shfl_xor(le, o);
+        above = min(above, uint32_t(__shfl_xor(above, o)));
+    }
+    if (lane == 0) {
+        sc.hist[wave] = le;
+        sc.hist[8 + wave] = above;
     }
     __syncthreads();
+    uint32_t tle = 0, tab = 0xffffffffu;
+    for (int w = 0; w < kMedThreads / 64; ++w) {
+        tle += sc.hist[w];
+        tab = min(tab, sc.hist[8 + w]);
+    }
+    const uint32_t v2 = tle >= r1 + 2 ? v1 : tab;
+    return 0.5 * (double(__uint_as_float(v1)) + double(__uint_as_float(v2)));
 }
 
-constexpr int kMedThreads = 256;
 constexpr int kMaxW = 8192;
-
-// Median of the sorted valid prefix of length w (mean of the middle pair for
-// even w), in FP64.
-__device__ __forceinline__ double median_sorted(const float *s, int w) {
-    return (w & 1) ? double(s[w >> 1]) : 0.5 * (double(s[(w >> 1) - 1]) + double(s[w >> 1]));
-}
 
 // One workgroup per block of W bins: X[k] from Z[k] and Z[M - k], then the
 // block's median power.
 __global__ __launch_bounds__(kMedThreads) void k_unpack_median(const float2 *__restrict__ Z,
                                                                int64_t M, float2 *__restrict__ X,
                                                                double *__restrict__ med, int W) {
-    __shared__ float s[kMaxW];
+    __shared__ uint32_t s[kMaxW];
+    __shared__ SelectScratch sc;
     const int t = threadIdx.x;
     const int64_t b0 = int64_t(blockIdx.x) * W;
     const int w = int(min(int64_t(W), M - b0));
     const double inv_n = 1.0 / double(2 * M);
-    for (int i = t; i < W; i += kMedThreads) {
-        float p = INFINITY;
-        if (i < w) {
-            const int64_t k = b0 + i;
-            float2 x = make_float2(0.f, 0.f);
-            if (k > 0) {
-                const float2 zk = Z[k];
-                const float2 zm = Z[M - k];
-                // E = (Z[k] + conj Z[M-k]) / 2,  O = (Z[k] - conj Z[M-k]) / (2i)
-                const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
-                const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
-                double sn, cs;
-                sincospi(-2.0 * double(k) * inv_n, &sn, &cs);
-                x = cadd(e, cmul(o, make_float2(float(cs), float(sn))));
-            }
-            X[k] = x;
-            p = cnorm(x);
+    for (int i = t; i < w; i += kMedThreads) {
+        const int64_t k = b0 + i;
+        float2 x = make_float2(0.f, 0.f);
+        if (k > 0) {
+            const float2 zk = Z[k];
+            const float2 zm = Z[M - k];
+            // E = (Z[k] + conj Z[M-k]) / 2,  O = (Z[k] - conj Z[M-k]) / (2i)
+            const float2 e = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+            const float2 o = make_float2(0.5f * (zk.y + zm.y), -0.5f * (zk.x - zm.x));
+            double sn, cs;
+            sincospi(-2.0 * double(k) * inv_n, &sn, &cs);
+            x = cadd(e, cmul(o, make_float2(float(cs), float(sn))));
         }
-        s[i] = p;
+        X[k] = x;
+        s[i] = __float_as_uint(cnorm(x));
     }
-    bitonic_sort_lds(s, W);
-    if (t == 0) med[blockIdx.x] = median_sorted(s, w);
+    __syncthreads();
+    const double m = median_select(s, w, sc);
+    if (t == 0) med[blockIdx.x] = m;
 }
 
 __global__ __launch_bounds__(kMedThreads) void k_median(const float2 *__restrict__ X, int64_t nb,
                                                         double *__restrict__ med, int W) {
-    __shared__ float s[kMaxW];
+    __shared__ uint32_t s[kMaxW];
+    __shared__ SelectScratch sc;
     const int t = threadIdx.x;
     const int64_t b0 = int64_t(blockIdx.x) * W;
     const int w = int(min(int64_t(W), nb - b0));
-    for (int i = t; i < W; i += kMedThreads) s[i] = i < w ? cnorm(X[b0 + i]) : INFINITY;
-    bitonic_sort_lds(s, W);
-    if (t == 0) med[blockIdx.x] = median_sorted(s, w);
+    for (int i = t; i < w; i += kMedThreads) s[i] = __float_as_uint(cnorm(X[b0 + i]));
+    __syncthreads();
+    const double m = median_select(s, w, sc);
+    if (t == 0) med[blockIdx.x] = m;
 }
 
 // -------------------------------------------------------- segment DFTs
