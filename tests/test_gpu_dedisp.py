@@ -20,6 +20,7 @@ def _dev(x):
     (1, 2048, 800.0, 0.0, 5e-4, [0.0, 100.0]),                           # one channel: all delays 0
     (257, 1 << 14, 1450.0, 1.171875, 2.56e-4, list(np.arange(0.0, 96.0, 3.0))),
     (64, 20000, 400.0, 1.5, 1e-4, [7.0]),                                # low band, long delays
+    (8, 40000, 400.0, 10.0, 1e-4, [0.0, 200.0, 3.0]),                    # 24,300-sample delays, unsorted DMs
 ])
 def test_dedisperse_bit_exact(gpu_lib, nchan, nsamp, f_top, foff, tsamp, dms):
     fil = synth.make_filterbank(nchan, nsamp, f_top, foff, tsamp, seed=nchan,
