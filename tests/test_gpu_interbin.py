@@ -121,3 +121,30 @@ def test_half_bin_options_and_plane_size(gpu_lib):
         plan.search(_dev(synth.make_series(1 << 14, seed=1).x), plane=small)
     plan.close()
     bank.close()
+
+
+def test_server_with_half_bins_and_refinement(gpu_lib):
+    # the served path carries the plan options: each result equals the search
+    # of the same series alone with the half-bin plane and refinement on
+    lens = [1 << 15, 1 << 14, 1 << 15, 1 << 15]
+    trials = [synth.make_series(n, seed=90 + i, pulsars=[synth.Pulsar(r=n / 7.1 + 0.5, z=3.1, amp=0.12, nharm=2)])
+              for i, n in enumerate(lens)]
+    bank = gpu_lib.make_templates(10.0, 2.0)
+    opts = dict(nharm_max=4, sigma=5.5, median_window=256, interbin=True, refine_levels=3)
+    alone = []
+    for t in trials:
+        p = gpu_lib.Plan(bank, t.nsamp, 256, **opts)
+        alone.append(p.search(_dev(t.x), cap=20000)[0])
+        p.close()
+    srv = gpu_lib.Server(bank, 256, 1 << 15, hbm_budget=0, max_slots=2, **opts)
+    for i, t in enumerate(trials):
+        srv.submit(t.x, tag=500 + i)
+    seen = {}
+    for _ in trials:
+        tag, c, n, lat = srv.poll(timeout_ms=60000, cap=20000)
+        seen[tag] = c
+    srv.close()
+    for i in range(len(trials)):
+        assert np.array_equal(seen[500 + i], alone[i])
+    assert sum(len(a) for a in alone) > 0
+    bank.close()
