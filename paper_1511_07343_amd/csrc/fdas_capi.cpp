@@ -663,6 +663,7 @@ int64_t fdas_plan_device_bytes(const fdas_plan_t *plan) {
         if (ws.nsamp) {
             const Geometry g = make_geometry(ws.nsamp, plan->S, plan->h, plan->W, cols_per_bin(plan));
             b += series_bytes(g, plan->S, plan->nz) + candidate_bytes(plan, g);
+            if (plan->td) b += ws.nsamp * 4;  // the resampled series
         }
     }
     return b;
