@@ -293,8 +293,8 @@ fdas_status fdas_plan_fetch_spectrum(fdas_plan_t *plan, void *spectrum_dev, doub
  * rounded to the nearest sample; tsamp in s; dms: host array of ndm values
  * >= 0, pc cm^-3) and writes out_dev[i][t] = sum_c fil[c][t + d[i][c]] for
  * t < nout (device float32[ndm][nout]; exact integer sums).  INVAL unless
- * nout <= nsamp - max d, 1 <= nchan, ndm <= 65536 and every frequency is
- * positive.  Synchronous; allocates 4 ndm nchan bytes of device memory for
+ * nout <= nsamp - max d, every delay < 2^31, 1 <= nchan, ndm <= 65536 and
+ * every frequency is positive.  Synchronous; allocates 4 ndm nchan bytes of device memory for
  * the call.  The output rows are series for fdas_search (nout a power of
  * two) or fdas_search_batch. */
 fdas_status fdas_dedisperse(const uint8_t *fil_dev, int32_t nchan, int64_t nsamp, double f_top, double foff,

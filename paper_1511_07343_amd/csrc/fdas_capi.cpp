@@ -905,8 +905,8 @@ fdas_status fdas_dedisperse(const uint8_t *fil_dev, int32_t nchan, int64_t nsamp
             const double f = f_top - foff * double(c);
             const double raw = kKdm * dms[i] * (1.0 / (f * f) - 1.0 / (f_top * f_top)) / tsamp;
             const double v = std::floor(raw + 0.5);
-            if (!(v < double(nsamp))) {
-                set_error("fdas_dedisperse: a delay exceeds the filterbank");
+            if (!(v < double(nsamp)) || v > 2147483647.0) {
+                set_error("fdas_dedisperse: a delay exceeds the filterbank (or 2^31 samples)");
                 return FDAS_E_INVAL;
             }
             d[size_t(i) * nchan + c] = int32_t(v);
