@@ -35,8 +35,11 @@ Prints one JSON line: the plain per-trial rate as ``value``, then
              matrix-core correlators, with power error and candidate
              agreement against the FP64 oracle on a band of bins;
 the roofline of the dominant kernel (the fused multiply / inverse DFT / power
-kernel, timed with HIP events on its own stream during the timed steps) and
-the FP64 CPU oracle timed on a bounded sample of the same trial.
+kernel, timed with HIP events on its own stream during the timed steps); the
+whole path against the HBM roof (``path_roofline``: the bytes the method must
+move per trial, series in, spectrum out and back, plane out and back, times
+the trial rate, over 8 TB/s) for the plain, batched and served rates; and the
+FP64 CPU oracle timed on a bounded sample of the same trial.
 """
 from __future__ import annotations
 
@@ -84,6 +87,22 @@ def correlate_bytes(nseg: int, nz: int, S: int, nb: int) -> float:
     2-bin block codes written once (4 nz Nb + nz Nb / 2), the segment spectra
     (8 nseg S) and the bank (8 nz S) read once."""
     return 4.0 * nz * nb + 0.5 * nz * nb + 8.0 * nseg * S + 8.0 * nz * S
+
+
+def path_bytes(nsamp: int, nz: int) -> float:
+    """Algorithmic HBM bytes of one whole search: the series read (4 N), the
+    spectrum written and read once (2 x 8 Nb), the f-fdot plane written once
+    and read once by the harmonic sums (2 x 4 nz Nb).  Bank and candidates are
+    negligible."""
+    nb = nsamp // 2
+    return 4.0 * nsamp + 16.0 * nb + 8.0 * nz * nb
+
+
+def path_roofline(bytes_per_trial: float, trials_per_s: float) -> dict:
+    """Whole-path throughput as a fraction of the HBM roof."""
+    ach = bytes_per_trial * trials_per_s / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_trial": round(bytes_per_trial)}
 
 
 def read_traffic():
@@ -151,7 +170,8 @@ def bench_batched(fdas, bank, xs, per_call: int):
             "trials_per_call": per_call, "ms_per_trial": round(1e3 * tb / len(xs), 4),
             "data": "64 distinct trials, seeds 1000-1063, 0-3 pulsars each, resident in HBM",
             "autotuned": {"segment": seg_b, "templates_per_block": tpb_b,
-                          "segment_dft_plus_correlate_ms": round(tune_ms, 4)}}
+                          "segment_dft_plus_correlate_ms": round(tune_ms, 4)},
+            "path_roofline": path_roofline(path_bytes(N, bank.nz), len(xs) / tb)}
 
 
 def _replay(fdas, srv, trace, ring, paced_speedup, inflight):
@@ -201,7 +221,9 @@ def bench_served(fdas, bank, ring, requests: int, paced: int, speedup: float):
     srv.poll(timeout_ms=120000)
     log(f"served: saturated replay of {len(trace)} requests")
     ts, lat_s, found = _replay(fdas, srv, trace, ring, 0.0, inflight=8)
+    mean_bytes = sum(path_bytes(e["nsamp"], bank.nz) for e in trace) / len(trace)
     out = {"value": round(len(trace) / ts, 3), "unit": "DM trials/s", "requests": len(trace),
+           "path_roofline": path_roofline(mean_bytes, len(trace) / ts),
            "mix": "20/30/50 % of 2^21/2^22/2^23 samples, 5 % with a pulsar",
            "arrival": "saturated: next request submitted while 8 are in flight; host series, PCIe included",
            "data": f"ring of {RING} seeded host series per length (one with a pulsar), recycled",
@@ -618,6 +640,8 @@ def main():
         "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 4),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 4)},
         "stages_ms": {k: round(v / max(ntimed, 1), 4) for k, v in stages.items()},
+        # the whole path against the HBM roof (bytes the method must move per trial)
+        "path_roofline": path_roofline(path_bytes(N, nz), value),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
                      "traffic": traffic, "kernel": "k_correlate (fused multiply, inverse DFT, power)",
