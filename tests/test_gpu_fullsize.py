@@ -115,3 +115,11 @@ def test_served_lengths_sampled(gpu_lib, nsamp):
     tr = synth.served_request({"nsamp": nsamp, "seed": 40007, "has_pulsar": True})
     n = _check(gpu_lib, tr.x, 200.0, 2.0, 8192, "fft", 1500, 12)
     assert n > 0
+
+
+def test_longest_series_sampled(gpu_lib):
+    # the longest series a plan takes (2^26 samples, 2^25 bins: the real DFT's
+    # largest four-step split) with a small bank
+    t = synth.make_series(1 << 26, seed=35, pulsars=[synth.Pulsar(r=12345678.4, z=9.0, amp=0.004, nharm=1)])
+    n = _check(gpu_lib, t.x, 20.0, 2.0, 8192, "fft", 1500, 13)
+    assert n > 0
