@@ -128,6 +128,65 @@ __global__ __launch_bounds__(fft_threads(LOG2M2)) void k_r2c_rows(const float2 *
     for (int m = 0; m < Sh::R; ++m) Z[k1 + (int64_t(t + Sh::NT * m) << log2m1)] = v[m];
 }
 
+// The same two passes with four columns (rows) per workgroup, column c
+// transformed by the threads t with t mod 4 = c (for 2^7 to 2^11 points): a
+// wave's load or store of one register then covers 16 rows of four adjacent
+// columns, 32 contiguous bytes each, instead of 64 rows of one column.  Each
+// column's LDS region is offset by 16 banks from the previous.
+constexpr int kR2cGroup = 4;
+
+template <class Sh>
+constexpr int r2c_region() {
+    return Sh::LDS_FLOAT2 + 8;
+}
+
+template <int LOG2M1>
+__global__ __launch_bounds__(fft_threads(LOG2M1) * kR2cGroup) void k_r2c_cols4(const float2 *__restrict__ z,
+                                                                                float2 *__restrict__ work,
+                                                                                int log2m2) {
+    using Sh = FftShape<LOG2M1, fft_threads(LOG2M1)>;
+    __shared__ float2 lds[kR2cGroup * r2c_region<Sh>()];
+    const int c = threadIdx.x & (kR2cGroup - 1);
+    const int t = threadIdx.x / kR2cGroup;
+    const int64_t M2 = int64_t(1) << log2m2;
+    const int64_t M = M2 << LOG2M1;
+    const int64_t n2 = xcd_spread(blockIdx.x, gridDim.x) * kR2cGroup + c;  // adjacent groups share lines
+    Twiddles<Sh, -1> tw;
+    tw.init(t);
+    float2 v[Sh::R];
+#pragma unroll
+    for (int m = 0; m < Sh::R; ++m) v[m] = z[n2 + M2 * (t + Sh::NT * m)];
+    fft_wg<Sh, -1>(v, lds + c * r2c_region<Sh>(), tw, t);
+#pragma unroll
+    for (int m = 0; m < Sh::R; ++m) {
+        const int64_t k1 = t + Sh::NT * m;
+        const int64_t idx = (n2 * k1) & (M - 1);
+        double s, co;
+        sincospi(-2.0 * double(idx) / double(M), &s, &co);
+        const float2 w = make_float2(float(co), float(s));
+        work[n2 + M2 * k1] = cmul(v[m], w);
+    }
+}
+
+template <int LOG2M2>
+__global__ __launch_bounds__(fft_threads(LOG2M2) * kR2cGroup) void k_r2c_rows4(const float2 *__restrict__ work,
+                                                                                float2 *__restrict__ Z,
+                                                                                int log2m1) {
+    using Sh = FftShape<LOG2M2, fft_threads(LOG2M2)>;
+    __shared__ float2 lds[kR2cGroup * r2c_region<Sh>()];
+    const int c = threadIdx.x & (kR2cGroup - 1);
+    const int t = threadIdx.x / kR2cGroup;
+    const int64_t k1 = xcd_spread(blockIdx.x, gridDim.x) * kR2cGroup + c;
+    Twiddles<Sh, -1> tw;
+    tw.init(t);
+    float2 v[Sh::R];
+#pragma unroll
+    for (int m = 0; m < Sh::R; ++m) v[m] = work[(k1 << LOG2M2) + t + Sh::NT * m];
+    fft_wg<Sh, -1>(v, lds + c * r2c_region<Sh>(), tw, t);
+#pragma unroll
+    for (int m = 0; m < Sh::R; ++m) Z[k1 + (int64_t(t + Sh::NT * m) << log2m1)] = v[m];
+}
+
 // ------------------------------------------------------ medians of |X|^2
 // Order statistics of W powers in LDS by radix selection on their bit
 // patterns (non-negative floats and +inf order as their unsigned bits): four
@@ -220,7 +279,7 @@ constexpr int kMaxW = 8192;
 __global__ __launch_bounds__(kMedThreads) void k_unpack_median(const float2 *__restrict__ Z,
                                                                int64_t M, float2 *__restrict__ X,
                                                                double *__restrict__ med, int W) {
-    __shared__ uint32_t s[kMaxW];
+    extern __shared__ uint32_t s[];  // W keys (dynamic: the block's size only)
     __shared__ SelectScratch sc;
     const int t = threadIdx.x;
     const int64_t b0 = int64_t(blockIdx.x) * W;
@@ -249,7 +308,7 @@ __global__ __launch_bounds__(kMedThreads) void k_unpack_median(const float2 *__r
 
 __global__ __launch_bounds__(kMedThreads) void k_median(const float2 *__restrict__ X, int64_t nb,
                                                         double *__restrict__ med, int W) {
-    __shared__ uint32_t s[kMaxW];
+    extern __shared__ uint32_t s[];  // W keys
     __shared__ SelectScratch sc;
     const int t = threadIdx.x;
     const int64_t b0 = int64_t(blockIdx.x) * W;
@@ -858,6 +917,16 @@ __global__ void k_zero_u32(uint32_t *__restrict__ p, int n) {
         default: return hipErrorInvalidValue; \
     }
 
+#define FDAS_SWITCH_LOG2_GROUPED(L, CALL) \
+    switch (L) {                          \
+        case 7: CALL(7); break;           \
+        case 8: CALL(8); break;           \
+        case 9: CALL(9); break;           \
+        case 10: CALL(10); break;         \
+        case 11: CALL(11); break;         \
+        default: return hipErrorInvalidValue; \
+    }
+
 }  // namespace
 
 hipError_t launch_dft(int log2n, int dir, int64_t batch, const float2 *in, float2 *out, hipStream_t st) {
@@ -884,16 +953,30 @@ hipError_t launch_r2c_packed(const float *x, int64_t nsamp, float2 *Z, float2 *w
 #undef CALL
         return hipGetLastError();
     }
-    const int l1 = (log2m + 1) / 2, l2 = log2m / 2;
+    const int l1 = (log2m + 1) / 2, l2 = log2m / 2;  // 7 <= l2 <= l1 <= 13
     const unsigned ncols = 1u << l2, nrows = 1u << l1;
-#define CALL(L) hipLaunchKernelGGL((k_r2c_cols<L>), dim3(ncols), dim3(fft_threads(L)), 0, st, z, work, l2);
-    FDAS_SWITCH_LOG2(l1, CALL)
+    if (l1 <= 11) {  // four columns per workgroup (ncols is a multiple of 4)
+#define CALL(L) hipLaunchKernelGGL((k_r2c_cols4<L>), dim3(ncols / kR2cGroup), dim3(fft_threads(L) * kR2cGroup), 0, st, \
+                           z, work, l2);
+        FDAS_SWITCH_LOG2_GROUPED(l1, CALL)
 #undef CALL
+    } else {
+#define CALL(L) hipLaunchKernelGGL((k_r2c_cols<L>), dim3(ncols), dim3(fft_threads(L)), 0, st, z, work, l2);
+        FDAS_SWITCH_LOG2(l1, CALL)
+#undef CALL
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-#define CALL(L) hipLaunchKernelGGL((k_r2c_rows<L>), dim3(nrows), dim3(fft_threads(L)), 0, st, work, Z, l1);
-    FDAS_SWITCH_LOG2(l2, CALL)
+    if (l2 <= 11) {
+#define CALL(L) hipLaunchKernelGGL((k_r2c_rows4<L>), dim3(nrows / kR2cGroup), dim3(fft_threads(L) * kR2cGroup), 0, st, \
+                           work, Z, l1);
+        FDAS_SWITCH_LOG2_GROUPED(l2, CALL)
 #undef CALL
+    } else {
+#define CALL(L) hipLaunchKernelGGL((k_r2c_rows<L>), dim3(nrows), dim3(fft_threads(L)), 0, st, work, Z, l1);
+        FDAS_SWITCH_LOG2(l2, CALL)
+#undef CALL
+    }
     return hipGetLastError();
 }
 
@@ -901,14 +984,16 @@ hipError_t launch_unpack_median(const float2 *Z, int64_t nsamp, float2 *X, doubl
     const int64_t M = nsamp / 2;
     if (W < 2 || W > kMaxW || (W & (W - 1))) return hipErrorInvalidValue;
     const int64_t nblk = (M + W - 1) / W;
-    hipLaunchKernelGGL(k_unpack_median, dim3(unsigned(nblk)), dim3(kMedThreads), 0, st, Z, M, X, med, W);
+    hipLaunchKernelGGL(k_unpack_median, dim3(unsigned(nblk)), dim3(kMedThreads), size_t(W) * sizeof(uint32_t), st, Z,
+                       M, X, med, W);
     return hipGetLastError();
 }
 
 hipError_t launch_median(const float2 *X, int64_t nb, double *med, int W, hipStream_t st) {
     if (W < 2 || W > kMaxW || (W & (W - 1))) return hipErrorInvalidValue;
     const int64_t nblk = (nb + W - 1) / W;
-    hipLaunchKernelGGL(k_median, dim3(unsigned(nblk)), dim3(kMedThreads), 0, st, X, nb, med, W);
+    hipLaunchKernelGGL(k_median, dim3(unsigned(nblk)), dim3(kMedThreads), size_t(W) * sizeof(uint32_t), st, X, nb,
+                       med, W);
     return hipGetLastError();
 }
 
