@@ -60,7 +60,8 @@ METRIC = "DM trials/sec (2^23 samp, z∈[-200,200]) plain vs served/batched; p50
 FP32_PEAK_TFLOPS = 157.3
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "correlate_ska_trial_traffic.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_1511_07343_amd", "csrc", f) for f in ("kernels.hip", "fft_wg.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1511_07343_amd", "csrc", f)
+                  for f in ("kernels.hip", "fft_wg.hpp", "device_common.hpp")]
 
 
 def log(msg):

@@ -18,10 +18,16 @@ __device__ __forceinline__ double median_curve(const double *__restrict__ med, i
     const double x = double(g);
     if (x <= c0 || nblk == 1) return med[0];
     if (x >= cl) return med[nblk - 1];
-    const int64_t b = int64_t(floor((x - c0) / double(W)));
+    // W is a power of two, so dividing by it is the exact multiply by 1 / W;
+    // the last interval (to the centre of a partial last block) is shorter,
+    // and its reciprocal width does not depend on g (computed once per
+    // thread when inlined in a loop)
+    const double inv_w = 1.0 / double(W);
+    const double inv_last = 1.0 / (cl - (c0 + double(nblk - 2) * double(W)));
+    const int64_t b = int64_t(floor((x - c0) * inv_w));
     const double cb = c0 + double(b) * double(W);
-    const double cb1 = (b + 1 == nblk - 1) ? cl : cb + double(W);
-    return med[b] + (med[b + 1] - med[b]) * ((x - cb) / (cb1 - cb));
+    const double f = (x - cb) * (b + 1 == nblk - 1 ? inv_last : inv_w);
+    return med[b] + (med[b + 1] - med[b]) * f;
 }
 
 // Screening code of a power: min(255, ceil(P / delta)) with code_inv = 1 / delta,
