@@ -564,7 +564,7 @@ def main():
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (this build runs the search on one MI355X); "
+        print(f"bench.py measures one GPU only (the search runs on one MI355X); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 

@@ -56,7 +56,7 @@ def compare_candidates(gpu: np.ndarray, orc, tol: dict | None = None) -> dict:
     """gpu: structured array (CAND_DTYPE); orc: oracle SearchResult with sums
     kept (or nharm_max 1).  tol: optional {nh: per-cell absolute error bound
     of the GPU's sums}, replacing the 1e-4 rule (for the 16-bit correlators).
-    Returns a report; report['ok'] is the verdict."""
+    Returns a report; report['ok'] says whether the two sets agree."""
     sums = dict(orc.sums)
     sums.setdefault(1, orc.plane)
     tol = tol or {}
