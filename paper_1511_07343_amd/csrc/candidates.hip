@@ -24,16 +24,17 @@ __device__ __forceinline__ uint32_t clamp_count(const uint32_t *count, uint32_t 
     return c < cap ? c : cap;
 }
 
-// key = (level << (bk + bz)) | (k << bz) | iz, level = log2(nharm), with k
-// in bk bits and iz in bz bits: ascending keys are ascending (nharm, k, iz).
+// key = (level nb + k) nz + iz, level = log2(nharm) in 0..4, k < nb, iz < nz:
+// ascending keys are ascending (nharm, k, iz), and all keys are below
+// 5 nb nz (32 bits, four 8-bit passes, at 2^23 samples and 201 templates).
 __global__ __launch_bounds__(256) void k_cand_keys(const DevCand *__restrict__ dc, const uint32_t *__restrict__ count,
-                                                   uint32_t cap, int bk, int bz, uint64_t *__restrict__ keys,
+                                                   uint32_t cap, int64_t nb, int nz, uint64_t *__restrict__ keys,
                                                    uint32_t *__restrict__ vals) {
     const uint32_t n = clamp_count(count, cap);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const DevCand c = dc[i];
         const uint64_t level = uint64_t(31 - __clz(c.nharm));
-        keys[i] = (level << (bk + bz)) | (uint64_t(uint32_t(c.k)) << bz) | uint64_t(uint32_t(c.iz));
+        keys[i] = (level * uint64_t(nb) + uint64_t(uint32_t(c.k))) * uint64_t(nz) + uint64_t(uint32_t(c.iz));
         vals[i] = i;
     }
 }
@@ -236,10 +237,10 @@ size_t cand_sort_scratch_bytes(uint32_t cap) {
 hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch, int nz,
                                     int64_t nb, int cpb, double zmax, double dz, fdas_cand *out, hipStream_t st) {
     if (cap == 0) return hipSuccess;
-    int bk = 1, bz = 1;
-    while ((int64_t(1) << bk) < nb) ++bk;
-    while ((1 << bz) < nz) ++bz;
-    const int passes = (3 + bk + bz + 7) / 8;
+    const uint64_t span = 5 * uint64_t(nb) * uint64_t(nz);  // keys are below this
+    int bits = 1;
+    while (bits < 64 && (uint64_t(1) << bits) < span) ++bits;
+    const int passes = (bits + 7) / 8;
     uint64_t *k0 = static_cast<uint64_t *>(scratch);
     uint64_t *k1 = k0 + cap;
     uint32_t *v0 = reinterpret_cast<uint32_t *>(k1 + cap);
@@ -247,7 +248,7 @@ hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, ui
     uint32_t *hist = reinterpret_cast<uint32_t *>((reinterpret_cast<uintptr_t>(v1 + cap) + 15) & ~uintptr_t(15));
     const uint64_t blocks = (uint64_t(cap) + 255) / 256;
     const unsigned grid = unsigned(blocks < 1024 ? blocks : 1024);
-    hipLaunchKernelGGL(k_cand_keys, dim3(grid), dim3(256), 0, st, dc, count, cap, bk, bz, k0, v0);
+    hipLaunchKernelGGL(k_cand_keys, dim3(grid), dim3(256), 0, st, dc, count, cap, nb, nz, k0, v0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // the order ends in v0 after an even number of passes, else in v1
