@@ -617,8 +617,8 @@ def cpu_baseline(trial, bins: int):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=16, help="trials per fdas_search_batch call")
     ap.add_argument("--batch-trials", type=int, default=64, help="distinct trials in the batched run (0 = skip)")
     ap.add_argument("--served", type=int, default=6000, help="requests of the served trace replayed (0 = skip)")
