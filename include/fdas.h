@@ -190,6 +190,12 @@ fdas_status fdas_plan(const fdas_bank *bank, int64_t nsamp, int32_t seg,
 fdas_status fdas_td_plan(int64_t nsamp, double alpha_max, int32_t nalpha, const fdas_opts *opts,
                          fdas_plan_t **out);
 int64_t fdas_plan_nbins(const fdas_plan_t *plan);
+/* Rows of the plan's plane (templates, or acceleration trials of a
+ * time-domain plan) and the trial value of row iz: z(iz) = -zmax + iz dz bins
+ * for a template plan (Sec. 2), alpha_iz as defined with fdas_td_plan for a
+ * time-domain plan.  NaN for a NULL plan or iz outside [0, rows). */
+int32_t fdas_plan_rows(const fdas_plan_t *plan);
+double fdas_plan_row_value(const fdas_plan_t *plan, int32_t iz);
 int64_t fdas_plan_device_bytes(const fdas_plan_t *plan);
 void fdas_plan_destroy(fdas_plan_t *plan);
 
@@ -217,6 +223,28 @@ fdas_status fdas_search(fdas_plan_t *plan, int32_t in_kind, const void *in_dev,
                         float *plane_dev, fdas_cand *cands_host, int64_t cap,
                         int64_t *ncands, void *hip_stream);
 
+/* One float32 series of nsamp samples in host memory through the same path
+ * as fdas_search with FDAS_IN_SERIES_F32, the host-to-device transfer of
+ * Sec. 4 step 1 included and overlapped as that step allows: the plan keeps
+ * two device input buffers (8 nsamp bytes, allocated on the first call) and a
+ * copy stream of its own.
+ *   series_host  the series to search now.  If the previous call on this plan
+ *                named the same pointer as its next_host, its copy has been
+ *                running since then and is waited for; otherwise it is copied
+ *                on hip_stream first.
+ *   next_host    NULL, or the series the caller will pass to the next call:
+ *                its copy into the other input buffer starts now on the copy
+ *                stream, overlapping this search.  The caller must keep that
+ *                memory unchanged until the next call returns.  With
+ *                page-locked memory (hipHostMalloc) the copy runs
+ *                asynchronously; with pageable memory it is still correct but
+ *                may not overlap.
+ * Other arguments, outputs, errors and the return point (candidates on the
+ * host) are those of fdas_search.  INVAL for a NULL series_host. */
+fdas_status fdas_search_host(fdas_plan_t *plan, const float *series_host, const float *next_host,
+                             float *plane_dev, fdas_cand *cands_host, int64_t cap, int64_t *ncands,
+                             void *hip_stream);
+
 /* Stage timing (measurement hook).  While enabled, fdas_search records a HIP
  * event pair around each stage on the stream the stage runs on and adds the
  * elapsed times (ms) into per-stage totals: 0 real-input DFT, 1 unpack and
@@ -235,8 +263,15 @@ fdas_status fdas_plan_stage_times(const fdas_plan_t *plan, double *ms_out, int64
 fdas_status fdas_plan_search_counts(const fdas_plan_t *plan, int64_t *out3);
 
 /* Several float32 series, possibly of different power-of-two lengths
- * nsamp[i] <= the plan's nsamp, through the hot path on one stream with their
- * stages overlapped (no plane is returned).  Trial i's candidates go to
+ * nsamp[i] <= the plan's nsamp, through the hot path (no plane is returned).
+ * The work is ordered after what hip_stream holds when the call is made, and
+ * hip_stream is ordered after it on return.  Internally consecutive trials
+ * alternate between two library-owned streams and two work buffers of their
+ * own, so that one trial's memory-bound harmonic sums overlap the next
+ * trial's correlation; each trial's launches are captured once per length in
+ * a HIP graph.  A batch leaves the buffers of fdas_search alone: the
+ * inspection, interpolation, refinement and work-count calls keep describing
+ * the plan's last fdas_search.  Trial i's candidates go to
  * cands_host + sum_{j<i} cap[j], count to ncands[i].  Returns the first error,
  * or OVERFLOW if any trial overflowed. */
 fdas_status fdas_search_batch(fdas_plan_t *plan, int32_t n, const float *const *series_dev,
@@ -277,6 +312,23 @@ fdas_status fdas_interp_power(fdas_plan_t *plan, int64_t n, const double *r, con
  * levels out of range or a record's nharm is not 1, 2, 4, 8 or 16; NOMEM if
  * the buffer cannot be allocated. */
 fdas_status fdas_refine(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t levels, void *hip_stream);
+
+/* fdas_refine without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, refinement and results as
+ * fdas_refine (bit-identical: the same kernels), but the records and their
+ * count are staged in a fixed device array that the library holds for the
+ * life of the process, FDAS_REFINE_NOALLOC_MAX records large (one array per
+ * GPU), instead of a per-call allocation; nothing is allocated or freed.
+ * INVAL when n > FDAS_REFINE_NOALLOC_MAX or when the current device is not
+ * the plan's, besides fdas_refine's own INVAL cases.  Every call on one GPU
+ * uses that GPU's one array: calls that overlap on a GPU (from several
+ * threads, or on several streams without ordering) race and must be
+ * serialised by the caller.  Synchronous.  For the copies to be capturable
+ * and asynchronous, cands should be page-locked host memory. */
+#define FDAS_REFINE_NOALLOC_MAX 16384
+fdas_status fdas_refine_noalloc(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t levels,
+                                void *hip_stream);
 
 /* Test hook: copy the last search's normalised spectrum (c64[Nb]) and block
  * medians (double[ceil(Nb/W)]) to device buffers; either pointer may be NULL. */

@@ -14,8 +14,8 @@ segmentation, no blocking:
 
 1. ``real_spectrum``   real-to-complex DFT of the series (Sec. 4, step 2).
 2. ``normalise``       block-median power normalisation (reading; paper silent).
-3. ``template_taps``   constant-acceleration response and its conjugate, the
-                        "inverse filter" (Sec. 2, the template of Ransom et al.).
+3. ``template_taps``   constant-acceleration response and its conjugate, which
+                        undoes the drift's spreading (Sec. 2, after Ransom et al.).
 4. ``correlate``       Eq. (1) summed directly (plain C, FP64).
 5. ``harmonic_sum``    incoherent sums over 1/2/4/8/16 harmonics (reading).
 6. ``thresholds``      single-trial sigma threshold per harmonic count (reading).

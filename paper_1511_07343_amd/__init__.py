@@ -88,14 +88,18 @@ def load():
         "fdas_dedisperse": (_c_i32, [_c_vp, _c_i32, _c_i64, _c_dbl, _c_dbl, _c_dbl, P(_c_dbl), _c_i32, _c_i64,
                                      _c_vp, _c_vp]),
         "fdas_plan_nbins": (_c_i64, [_c_vp]),
+        "fdas_plan_rows": (_c_i32, [_c_vp]),
+        "fdas_plan_row_value": (_c_dbl, [_c_vp, _c_i32]),
         "fdas_plan_device_bytes": (_c_i64, [_c_vp]),
         "fdas_plan_destroy": (None, [_c_vp]),
         "fdas_search": (_c_i32, [_c_vp, _c_i32, _c_vp, _c_vp, P(_Cand), _c_i64, P(_c_i64), _c_vp]),
+        "fdas_search_host": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp, P(_Cand), _c_i64, P(_c_i64), _c_vp]),
         "fdas_search_batch": (_c_i32, [_c_vp, _c_i32, P(_c_vp), P(_c_i64), P(_Cand), P(_c_i64),
                                        P(_c_i64), _c_vp]),
         "fdas_plan_fetch_spectrum": (_c_i32, [_c_vp, _c_vp, _c_vp, _c_vp]),
         "fdas_interp_power": (_c_i32, [_c_vp, _c_i64, P(_c_dbl), P(_c_dbl), P(_c_i32), P(_c_dbl), _c_vp]),
         "fdas_refine": (_c_i32, [_c_vp, _c_vp, _c_i64, _c_i32, _c_vp]),
+        "fdas_refine_noalloc": (_c_i32, [_c_vp, _c_vp, _c_i64, _c_i32, _c_vp]),
         "fdas_plan_enable_timing": (_c_i32, [_c_vp, _c_i32]),
         "fdas_plan_stage_times": (_c_i32, [_c_vp, P(_c_dbl), P(_c_i64)]),
         "fdas_plan_search_counts": (_c_i32, [_c_vp, P(_c_i64)]),
@@ -262,6 +266,7 @@ class Plan:
         self.nsamp, self.seg = int(nsamp), int(seg)
         self.opts = o
         self._buf = _CandBuffer()
+        self._staged = None
 
     @property
     def nbins(self) -> int:
@@ -292,6 +297,44 @@ class Plan:
         st = load().fdas_search(self._h, kind, ctypes.c_void_p(inp.data_ptr()),
                                 ctypes.c_void_p(plane.data_ptr() if plane is not None else 0),
                                 _CandBuffer.ptr(buf), cap, ctypes.byref(n), _stream_handle(stream))
+        _check(st, allow=(-4,) if allow_overflow else ())
+        m = min(n.value, cap)
+        return (buf[:m] if out is not None else buf[:m].copy()), n.value
+
+    def search_host(self, series, next=None, plane=None, cap: int = 1 << 22, stream=None,
+                    allow_overflow: bool = False, out: Optional[np.ndarray] = None):
+        """Search a float32 series held in host memory (a numpy array or a CPU
+        tensor, page-locked for the copy to overlap), copying it to the device
+        as part of the call; ``next`` (same kinds, may be None) is the series of
+        the following call, whose copy starts now and overlaps this search.
+        The binding keeps ``next`` alive until that call.  Returns
+        (candidates, n_found) like ``search``."""
+        def ptr(a):
+            if a is None:
+                return 0, None
+            if hasattr(a, "data_ptr"):
+                if a.is_cuda or a.dtype != __import__("torch").float32 or not a.is_contiguous():
+                    raise TypeError("host series must be a contiguous float32 CPU tensor or array")
+                if a.numel() != self.nsamp:
+                    raise ValueError(f"host series must hold {self.nsamp} samples")
+                return a.data_ptr(), a
+            a = np.ascontiguousarray(a, dtype=np.float32)
+            if a.shape != (self.nsamp,):
+                raise ValueError(f"host series must hold {self.nsamp} samples")
+            return a.ctypes.data, a
+        p_cur, keep_cur = ptr(series)
+        p_next, keep_next = ptr(next)
+        buf = out if out is not None else self._buf.get(max(cap, 1))
+        if out is not None:
+            cap = min(cap, out.shape[0])
+        if plane is not None and plane.numel() * plane.element_size() < 4 * self.rows * self.plane_columns:
+            raise ValueError(f"plane must hold float32[{self.rows}][{self.plane_columns}]")
+        n = ctypes.c_int64()
+        st = load().fdas_search_host(self._h, ctypes.c_void_p(p_cur), ctypes.c_void_p(p_next),
+                                     ctypes.c_void_p(plane.data_ptr() if plane is not None else 0),
+                                     _CandBuffer.ptr(buf), cap, ctypes.byref(n), _stream_handle(stream))
+        self._staged = keep_next  # its copy is in flight until the next call
+        del keep_cur
         _check(st, allow=(-4,) if allow_overflow else ())
         m = min(n.value, cap)
         return (buf[:m] if out is not None else buf[:m].copy()), n.value
@@ -346,6 +389,16 @@ class Plan:
                                   int(levels), _stream_handle(stream)))
         return out
 
+    REFINE_NOALLOC_MAX = 16384  # FDAS_REFINE_NOALLOC_MAX
+
+    def refine_noalloc(self, cands: np.ndarray, levels: int = 6, stream=None) -> np.ndarray:
+        """``refine`` through the allocation-free entry point (records staged in
+        the library's fixed device array; at most REFINE_NOALLOC_MAX)."""
+        out = np.ascontiguousarray(cands, dtype=CAND_DTYPE).copy()
+        _check(load().fdas_refine_noalloc(self._h, ctypes.c_void_p(out.ctypes.data if out.size else 0), out.size,
+                                          int(levels), _stream_handle(stream)))
+        return out
+
     STAGES = ("r2c", "unpack_median", "segment_dft", "correlate", "harmonic_sum", "refine")
 
     def enable_timing(self, enable: bool = True):
@@ -394,13 +447,14 @@ class TdPlan(Plan):
         self.alpha_max = float(alpha_max)
         self.opts = o
         self._buf = _CandBuffer()
+        self._staged = None
 
     @property
     def alphas(self) -> np.ndarray:
-        if self.rows == 1:
-            return np.zeros(1)
-        d = 2.0 * self.alpha_max / (self.rows - 1)
-        return -self.alpha_max + d * np.arange(self.rows, dtype=np.float64)
+        """The acceleration trial of every plane row, as the library defines them."""
+        lib = load()
+        return np.array([lib.fdas_plan_row_value(self._h, i) for i in range(lib.fdas_plan_rows(self._h))],
+                        dtype=np.float64)
 
 
 class Server:

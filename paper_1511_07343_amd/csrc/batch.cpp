@@ -11,14 +11,18 @@
 
 namespace fdas {
 
+// Workspace of batch slot i (0 or 1): plan->ws[1 + i], never the buffers of
+// fdas_search.
+static fdas::Workspace &slot_ws(fdas_plan_s *p, int i) { return p->ws[size_t(1 + i)]; }
+
 static fdas_status ensure_batch_resources(fdas_plan_s *p) {
     for (int i = 0; i < 2; ++i) {
-        if (!p->ws[i].nsamp) {
-            fdas_status s = alloc_workspace(p, p->ws[i], p->nsamp);
+        if (!slot_ws(p, i).nsamp) {
+            fdas_status s = alloc_workspace(p, slot_ws(p, i), p->nsamp);
             if (s != FDAS_OK) return s;
         }
-        if (!p->ws[i].series) {
-            hipError_t e = hipMalloc(reinterpret_cast<void **>(&p->ws[i].series), size_t(p->nsamp) * 4);
+        if (!slot_ws(p, i).series) {
+            hipError_t e = hipMalloc(reinterpret_cast<void **>(&slot_ws(p, i).series), size_t(p->nsamp) * 4);
             if (e != hipSuccess) {
                 (void)hipGetLastError();
                 set_error("hipMalloc batch input buffer");
@@ -46,7 +50,7 @@ static fdas_status slot_graph(fdas_plan_s *p, int i, int64_t nsamp, hipGraphExec
         *out = it->second;
         return FDAS_OK;
     }
-    Workspace &ws = p->ws[size_t(i)];
+    Workspace &ws = slot_ws(p, i);
     hipStream_t st = p->aux[size_t(i)];
     hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(p, e, "begin capture");
@@ -128,7 +132,7 @@ extern "C" fdas_status fdas_search_batch(fdas_plan_t *plan, int32_t n, const flo
         const int slot = j % 2;
         hipError_t ee = hipEventSynchronize(plan->events[slot]);
         if (ee != hipSuccess) return hip_fail(plan, ee, "batch trial");
-        fdas_status r = copy_candidates(plan, plan->ws[slot], cands_host + offset[size_t(j)], cap[j], &ncands[j],
+        fdas_status r = copy_candidates(plan, slot_ws(plan, slot), cands_host + offset[size_t(j)], cap[j], &ncands[j],
                                         plan->aux[slot]);
         if (r == FDAS_E_OVERFLOW) {
             overflow = true;
@@ -143,7 +147,7 @@ extern "C" fdas_status fdas_search_batch(fdas_plan_t *plan, int32_t n, const flo
             first_err = finish(i - 2);
             if (first_err != FDAS_OK) break;
         }
-        Workspace &ws = plan->ws[slot];
+        Workspace &ws = slot_ws(plan, slot);
         hipGraphExec_t exec = nullptr;
         first_err = slot_graph(plan, slot, nsamp[i], &exec);
         if (first_err != FDAS_OK) break;

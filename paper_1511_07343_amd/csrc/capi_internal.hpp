@@ -69,19 +69,31 @@ struct fdas_plan_s {
     int32_t corr = 0;          // FDAS_CORR_*
     bool td = false;           // time-domain resampling search: nz trials alpha = -zmax + iz dz
     int num_cu = 256;          // compute units of the device (matrix correlator grid)
-    std::array<fdas::Workspace, 2> ws{};
+    // ws[0]: fdas_search; ws[1], ws[2]: the batched path's two slots, so that
+    // a batch leaves the single-search buffers (and what the inspection,
+    // interpolation and refinement calls read from them) untouched
+    std::array<fdas::Workspace, 3> ws{};
     std::array<hipStream_t, 2> aux{};
     std::array<hipEvent_t, 4> events{};
     // batched path: captured per-trial launch sequence, per slot and length
     std::array<std::map<int64_t, hipGraphExec_t>, 2> graphs{};
     bool broken = false;
+    // fdas_search_host: two device input buffers filled on a copy stream of
+    // the plan's own; the host pointer whose copy into in_dev[staged_slot]
+    // was started by the previous call (event in_ready[staged_slot])
+    std::array<float *, 2> in_dev{};
+    hipStream_t copy_stream = nullptr;
+    std::array<hipEvent_t, 2> in_ready{};
+    const float *staged_host = nullptr;
+    int staged_slot = -1;
     // stage timing (fdas_plan_enable_timing)
     bool timing = false;
     std::array<hipEvent_t, FDAS_NSTAGES + 1> tev{};
     std::array<double, FDAS_NSTAGES> stage_ms{};
     int64_t timed = 0;
-    bool searched = false;  // a search has been enqueued
-    // last search, for the inspection hook
+    // last fdas_search (not a batch or served request), for the inspection,
+    // interpolation and refinement calls and the work counts
+    bool searched = false;
     const float2 *last_X = nullptr;
     const double *last_med = nullptr;
     int64_t last_nb = 0;
@@ -102,9 +114,16 @@ int64_t series_bytes(const Geometry &g, int32_t S, int32_t nz);
 int64_t candidate_bytes(const fdas_plan_s *p, const Geometry &g);
 fdas_status alloc_workspace(fdas_plan_s *p, Workspace &ws, int64_t nsamp);
 void destroy_workspace(Workspace &ws);
+// Enqueue the whole per-series path on st.  Leaves the plan's last-search
+// state alone; X_out / med_out (may be NULL) receive the normalised
+// spectrum's source buffer and medians the search used (NULL for a
+// time-domain plan, medians NULL for an already normalised spectrum).
 fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &g, int32_t in_kind,
                            const void *in_dev, float *plane, DevCand *dcands, uint32_t *dcount, hipStream_t st,
-                           bool timed = false);
+                           bool timed = false, const float2 **X_out = nullptr, const double **med_out = nullptr);
+// Trial value of plane row iz: the drift z(iz) of a template plan, the
+// acceleration trial alpha_iz of a time-domain plan.
+double row_value(const fdas_plan_s *p, int32_t iz);
 fdas_status accumulate_timing(fdas_plan_s *p);
 // Copy a finished search's sorted candidates (count already in *ws.h_count
 // after the stream reached it) into out[0..cap); sets *ncands to the true count.

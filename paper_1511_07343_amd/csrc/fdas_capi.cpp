@@ -128,7 +128,7 @@ static fdas_status enqueue_td_search(fdas_plan_s *p, const Workspace &ws, const 
     hipError_t e = mark(0);
     const float *x = static_cast<const float *>(in_dev);
     for (int32_t iz = 0; iz < p->nz && e == hipSuccess; ++iz) {
-        const double alpha = p->nz > 1 ? -p->zmax + p->dz * double(iz) : 0.0;
+        const double alpha = row_value(p, iz);
         e = launch_td_resample(x, g.nsamp, alpha, ws.resampled, st);
         if (e == hipSuccess) e = launch_r2c_packed(ws.resampled, g.nsamp, ws.Z, ws.work, st);
         if (e == hipSuccess) e = launch_unpack_median(ws.Z, g.nsamp, ws.X, ws.med, p->W, st);
@@ -147,18 +147,21 @@ static fdas_status enqueue_td_search(fdas_plan_s *p, const Workspace &ws, const 
     if (e == hipSuccess) e = launch_td_drift(dcount, p->cand_cap, p->zmax, p->nz, ws.final, st);
     for (int i = 5; i <= FDAS_NSTAGES && e == hipSuccess; ++i) e = mark(i);
     if (e != hipSuccess) return hip_fail(p, e, "time-domain harmonic sums");
-    p->last_X = nullptr;  // no spectrum for refinement
-    p->last_med = nullptr;
-    p->last_nb = g.nb;
-    p->searched = true;
     return FDAS_OK;
 }
 
 // Run the whole per-series path on `st`, writing the plane into `plane` and
 // candidates into the plan's device buffers (count at *dcount).
+double row_value(const fdas_plan_s *p, int32_t iz) {
+    if (p->td && p->nz == 1) return 0.0;
+    return -p->zmax + p->dz * double(iz);
+}
+
 fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &g, int32_t in_kind,
                            const void *in_dev, float *plane, DevCand *dcands, uint32_t *dcount,
-                           hipStream_t st, bool timed) {
+                           hipStream_t st, bool timed, const float2 **X_out, const double **med_out) {
+    if (X_out) *X_out = nullptr;
+    if (med_out) *med_out = nullptr;
     if (p->td) return enqueue_td_search(p, ws, g, in_kind, in_dev, plane, dcands, dcount, st, timed);
     hipError_t e;
     const float2 *X = nullptr;
@@ -218,10 +221,8 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
         if (e != hipSuccess) return hip_fail(p, e, "candidate refinement");
     }
     if ((e = mark(6)) != hipSuccess) return hip_fail(p, e, "timing event");
-    p->last_X = X;
-    p->last_med = med;
-    p->last_nb = g.nb;
-    p->searched = true;
+    if (X_out) *X_out = X;
+    if (med_out) *med_out = med;
     return FDAS_OK;
 }
 
@@ -654,6 +655,13 @@ fdas_status fdas_td_plan(int64_t nsamp, double alpha_max, int32_t nalpha, const 
 
 int64_t fdas_plan_nbins(const fdas_plan_t *plan) { return plan ? plan->nsamp / 2 : 0; }
 
+int32_t fdas_plan_rows(const fdas_plan_t *plan) { return plan ? plan->nz : 0; }
+
+double fdas_plan_row_value(const fdas_plan_t *plan, int32_t iz) {
+    if (!plan || iz < 0 || iz >= plan->nz) return NAN;
+    return row_value(plan, iz);
+}
+
 int64_t fdas_plan_device_bytes(const fdas_plan_t *plan) {
     if (!plan) return 0;
     int64_t b = plan->td ? 0
@@ -671,6 +679,18 @@ int64_t fdas_plan_device_bytes(const fdas_plan_t *plan) {
 
 void fdas_plan_destroy(fdas_plan_t *plan) {
     if (!plan) return;
+    if (plan->copy_stream) {
+        (void)hipStreamSynchronize(plan->copy_stream);  // a prefetch may still write in_dev
+        (void)hipStreamDestroy(plan->copy_stream);
+    }
+    for (float *&b : plan->in_dev) {
+        if (b) (void)hipFree(b);
+        b = nullptr;
+    }
+    for (hipEvent_t &ev : plan->in_ready) {
+        if (ev) (void)hipEventDestroy(ev);
+        ev = nullptr;
+    }
     for (Workspace &ws : plan->ws) destroy_workspace(ws);
     for (hipStream_t &s : plan->aux) {
         if (s) (void)hipStreamDestroy(s);
@@ -715,14 +735,93 @@ fdas_status fdas_search(fdas_plan_t *plan, int32_t in_kind, const void *in_dev, 
     const Geometry g = make_geometry(plan->nsamp, plan->S, plan->h, plan->W, cols_per_bin(plan));
     float *plane = plane_dev ? plane_dev : ws.plane;
     const bool timed = plan->timing;
-    fdas_status s = enqueue_search(plan, ws, g, in_kind, in_dev, plane, ws.cands, ws.count, st, timed);
+    const float2 *X = nullptr;
+    const double *med = nullptr;
+    plan->searched = false;
+    plan->last_X = nullptr;
+    plan->last_med = nullptr;
+    fdas_status s = enqueue_search(plan, ws, g, in_kind, in_dev, plane, ws.cands, ws.count, st, timed, &X, &med);
     if (s != FDAS_OK) return s;
+    plan->last_X = X;
+    plan->last_med = med;
+    plan->last_nb = g.nb;
+    plan->searched = true;
     s = collect(plan, ws, cands_host, cap, ncands, st);
     if (timed && (s == FDAS_OK || s == FDAS_E_OVERFLOW)) {
         const fdas_status t = accumulate_timing(plan);
         if (t != FDAS_OK) return t;
     }
     return s;
+}
+
+fdas_status fdas_search_host(fdas_plan_t *plan, const float *series_host, const float *next_host,
+                             float *plane_dev, fdas_cand *cands_host, int64_t cap, int64_t *ncands,
+                             void *hip_stream) {
+    if (!plan || !series_host || cap < 0 || (cap > 0 && !cands_host)) {
+        set_error("bad plan, host series or candidate buffer");
+        return FDAS_E_INVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(plane_dev) % 16 != 0) {
+        set_error("plane_dev must be 16-byte aligned");
+        return FDAS_E_INVAL;
+    }
+    if (plan->broken) {
+        set_error("plan is unusable after a device error");
+        return FDAS_E_DEVICE;
+    }
+    const size_t bytes = size_t(plan->nsamp) * sizeof(float);
+    hipError_t e = hipSuccess;
+    if (!plan->copy_stream) {
+        for (float *&b : plan->in_dev) {
+            e = hipMalloc(reinterpret_cast<void **>(&b), bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                for (float *&x : plan->in_dev) {
+                    if (x) (void)hipFree(x);
+                    x = nullptr;
+                }
+                set_error("hipMalloc host-series input buffers");
+                return FDAS_E_NOMEM;
+            }
+        }
+        for (hipEvent_t &ev : plan->in_ready) {
+            if (!ev && (e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+                return hip_fail(plan, e, "event create");
+        }
+        if ((e = hipStreamCreateWithFlags(&plan->copy_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(plan, e, "copy stream create");
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    int slot;
+    if (plan->staged_slot >= 0 && plan->staged_host == series_host) {
+        // the previous call started this copy on the copy stream
+        slot = plan->staged_slot;
+        if ((e = hipStreamWaitEvent(st, plan->in_ready[size_t(slot)], 0)) != hipSuccess)
+            return hip_fail(plan, e, "wait for the staged series");
+    } else {
+        // a staged series that is not used is dropped once its copy is done
+        slot = plan->staged_slot >= 0 ? plan->staged_slot : 0;
+        if (plan->staged_slot >= 0 && (e = hipStreamWaitEvent(st, plan->in_ready[size_t(slot)], 0)) != hipSuccess)
+            return hip_fail(plan, e, "wait for the staged series");
+        if ((e = hipMemcpyAsync(plan->in_dev[size_t(slot)], series_host, bytes, hipMemcpyHostToDevice, st)) !=
+            hipSuccess)
+            return hip_fail(plan, e, "copy series to the device");
+    }
+    plan->staged_host = nullptr;
+    plan->staged_slot = -1;
+    if (next_host) {
+        // every earlier search has returned (each call ends with a stream
+        // synchronisation), so the other buffer is no longer read
+        const int ns = 1 - slot;
+        if ((e = hipMemcpyAsync(plan->in_dev[size_t(ns)], next_host, bytes, hipMemcpyHostToDevice,
+                                plan->copy_stream)) != hipSuccess ||
+            (e = hipEventRecord(plan->in_ready[size_t(ns)], plan->copy_stream)) != hipSuccess)
+            return hip_fail(plan, e, "start the next series' copy");
+        plan->staged_host = next_host;
+        plan->staged_slot = ns;
+    }
+    return fdas_search(plan, FDAS_IN_SERIES_F32, plan->in_dev[size_t(slot)], plane_dev, cands_host, cap, ncands,
+                       hip_stream);
 }
 
 fdas_status fdas_plan_enable_timing(fdas_plan_t *plan, int32_t enable) {
@@ -836,7 +935,8 @@ fdas_status fdas_interp_power(fdas_plan_t *plan, int64_t n, const double *r, con
     return FDAS_OK;
 }
 
-fdas_status fdas_refine(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t levels, void *hip_stream) {
+// Argument checks shared by fdas_refine and fdas_refine_noalloc.
+static fdas_status check_refine_args(const fdas_plan_t *plan, const fdas_cand *cands, int64_t n, int32_t levels) {
     if (plan && plan->td) {
         set_error("refinement needs a template (FDAS) plan");
         return FDAS_E_INVAL;
@@ -856,6 +956,61 @@ fdas_status fdas_refine(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t 
             return FDAS_E_INVAL;
         }
     }
+    return FDAS_OK;
+}
+
+// Records dc and count dn on the device (either buffer the caller provides):
+// copy in, refine, copy back, wait.
+static hipError_t refine_on_device(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t levels, fdas_cand *dc,
+                                   uint32_t *dn, const uint32_t *nn_host, hipStream_t st) {
+    const size_t bytes = size_t(n) * sizeof(fdas_cand);
+    hipError_t e;
+    if ((e = hipMemcpyAsync(dc, cands, bytes, hipMemcpyHostToDevice, st)) == hipSuccess &&
+        (e = hipMemcpyAsync(dn, nn_host, sizeof(uint32_t), hipMemcpyHostToDevice, st)) == hipSuccess &&
+        (e = launch_refine(plan->last_X, plan->last_med, plan->W, plan->last_nb, plan->h, plan->izc, plan->dz,
+                           plan->zmax, cols_per_bin(plan), levels, dn, uint32_t(n), dc, 4 * plan->num_cu, st)) ==
+            hipSuccess &&
+        (e = hipMemcpyAsync(cands, dc, bytes, hipMemcpyDeviceToHost, st)) == hipSuccess) {
+        e = hipStreamSynchronize(st);
+    }
+    return e;
+}
+
+fdas_status fdas_refine_noalloc(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t levels, void *hip_stream) {
+    fdas_status s = check_refine_args(plan, cands, n, levels);
+    if (s != FDAS_OK) return s;
+    if (n > FDAS_REFINE_NOALLOC_MAX) {
+        set_error("fdas_refine_noalloc: more than FDAS_REFINE_NOALLOC_MAX (16384) records; use fdas_refine");
+        return FDAS_E_INVAL;
+    }
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "fdas_refine_noalloc: current device");
+    if (dev != plan->device) {
+        set_error("fdas_refine_noalloc: the current device is not the plan's");
+        return FDAS_E_INVAL;
+    }
+    if (n == 0) return FDAS_OK;
+    void *scr = nullptr;
+    size_t scr_bytes = 0;
+    e = refine_noalloc_scratch(&scr, &scr_bytes);
+    if (e != hipSuccess) return hip_fail(plan, e, "fdas_refine_noalloc: scratch address");
+    fdas_cand *dc = static_cast<fdas_cand *>(scr);
+    uint32_t *dn = reinterpret_cast<uint32_t *>(static_cast<char *>(scr) + size_t(FDAS_REFINE_NOALLOC_MAX) *
+                                                                              sizeof(fdas_cand));
+    if (size_t(FDAS_REFINE_NOALLOC_MAX) * sizeof(fdas_cand) + sizeof(uint32_t) > scr_bytes) {
+        set_error("fdas_refine_noalloc: scratch array too small");
+        return FDAS_E_DEVICE;
+    }
+    const uint32_t nn = uint32_t(n);
+    e = refine_on_device(plan, cands, n, levels, dc, dn, &nn, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(plan, e, "refine");
+    return FDAS_OK;
+}
+
+fdas_status fdas_refine(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t levels, void *hip_stream) {
+    fdas_status s = check_refine_args(plan, cands, n, levels);
+    if (s != FDAS_OK) return s;
     if (n == 0) return FDAS_OK;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const size_t bytes = size_t(n) * sizeof(fdas_cand);
@@ -869,13 +1024,7 @@ fdas_status fdas_refine(fdas_plan_t *plan, fdas_cand *cands, int64_t n, int32_t 
     fdas_cand *dc = reinterpret_cast<fdas_cand *>(buf);
     uint32_t *dn = reinterpret_cast<uint32_t *>(buf + bytes);
     const uint32_t nn = uint32_t(n);
-    if ((e = hipMemcpyAsync(dc, cands, bytes, hipMemcpyHostToDevice, st)) == hipSuccess &&
-        (e = hipMemcpyAsync(dn, &nn, sizeof(nn), hipMemcpyHostToDevice, st)) == hipSuccess &&
-        (e = launch_refine(plan->last_X, plan->last_med, plan->W, plan->last_nb, plan->h, plan->izc, plan->dz,
-                           plan->zmax, cols_per_bin(plan), levels, dn, nn, dc, 4 * plan->num_cu, st)) == hipSuccess &&
-        (e = hipMemcpyAsync(cands, dc, bytes, hipMemcpyDeviceToHost, st)) == hipSuccess) {
-        e = hipStreamSynchronize(st);
-    }
+    e = refine_on_device(plan, cands, n, levels, dc, dn, &nn, st);
     const hipError_t ef = hipFree(buf);
     if (e != hipSuccess) return hip_fail(plan, e, "refine");
     if (ef != hipSuccess) return hip_fail(plan, ef, "free");

@@ -135,6 +135,9 @@ hipError_t launch_td_drift(const uint32_t *count, uint32_t cap, double alpha_max
 // sigma of the records are replaced by those of the final point.  The
 // spectrum is X scaled by sqrt(ln2 / m(k)) (X itself when med is NULL), as in
 // the search.  A persistent grid of `workgroups` workgroups.
+// Device address (on the current device) and size of the file-scope scratch
+// array of the allocation-free refinement; looked up once per device.
+hipError_t refine_noalloc_scratch(void **out, size_t *bytes);
 hipError_t launch_refine(const float2 *X, const double *med, int W, int64_t nb, int h, int izc, double dz,
                          double zmax, int cpb, int levels, const uint32_t *count, uint32_t cap, fdas_cand *cands,
                          int workgroups, hipStream_t st);

@@ -9,6 +9,7 @@
 #include "kernels.hpp"
 
 #include <cmath>
+#include <mutex>
 
 namespace fdas {
 
@@ -339,6 +340,34 @@ hipError_t launch_refine(const float2 *X, const double *med, int W, int64_t nb, 
                        make_spectrum(X, med, W, nb), h, izc, dz, zmax, cpb, levels, count, cap, cands);
     hipLaunchKernelGGL(k_refine_sigma, dim3(unsigned(workgroups)), dim3(256), 0, st, count, cap, cands);
     return hipGetLastError();
+}
+
+// Records and count of fdas_refine_noalloc: a file-scope device array, one
+// copy per GPU, held until the process ends.  Host code never hands the
+// array's name to a kernel or a copy (on the host it is only a stand-in for
+// the symbol); it uses the device address hipGetSymbolAddress returns for
+// the current device, looked up once per device and kept.
+constexpr size_t kRefineScratchBytes = size_t(FDAS_REFINE_NOALLOC_MAX) * sizeof(fdas_cand) + 256;
+static __device__ __align__(256) unsigned char scratch[kRefineScratchBytes];
+
+hipError_t refine_noalloc_scratch(void **out, size_t *bytes) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    *bytes = kRefineScratchBytes;
+    return hipSuccess;
 }
 
 hipError_t launch_interp_points(const float2 *X, const double *med, int W, int64_t nb, int h, const double *r,

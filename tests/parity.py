@@ -86,3 +86,80 @@ def compare_candidates(gpu: np.ndarray, orc, tol: dict | None = None) -> dict:
                 missing=missing, extra=extra, borderline=border, n_gpu=len(g), n_orc=len(o),
                 max_power_err=worst * (REL if not tol else 1.0), max_err_fraction=worst,
                 sorted=keys == sorted(keys))
+
+
+# ------------------------------------------------ banded full-size checks
+def band_sums(Xh: np.ndarray, taps: np.ndarray, izc: int, k0: int, k1: int, nhs):
+    """The oracle's harmonic sums S_nh over every plane row for the columns
+    [a, b) = [k0 - 1, k1 + 1) clipped to the plane (one column of margin for
+    the 3x3 neighbours of [k0, k1)).
+
+    Each sum needs fraction m/16 (m = 16 j / nh) of every column: the
+    columns floor((m k + 8) / 16), k in [a, b), of all rows.  Those are
+    correlated directly by the oracle (Eq. (1), FP64) on a zero-padded slice
+    of the normalised spectrum, and the sums are taken with the oracle's own
+    harmonic index maps.  Returns (a, {nh: S[nz, b - a]})."""
+    import oracle as O
+    nb = Xh.shape[0]
+    nz, ntap = taps.shape
+    h = (ntap - 1) // 2
+    a, b = max(k0 - 1, 0), min(k1 + 1, nb)
+    ks = np.arange(a, b, dtype=np.int64)
+    cache = {}
+
+    def cols(m):
+        if m not in cache:
+            c0 = (m * a + 8) // 16
+            c1 = (m * (b - 1) + 8) // 16 + 1
+            lo, hi = c0 - h, c1 + h
+            seg = np.zeros(hi - lo, dtype=np.complex128)
+            s0, s1 = max(lo, 0), min(hi, nb)
+            seg[s0 - lo:s1 - lo] = Xh[s0:s1]
+            cache[m] = (c0, O.correlate(seg, taps)[:, h:h + (c1 - c0)])
+        return cache[m]
+
+    rows = np.arange(nz, dtype=np.int64)
+    out = {}
+    for nh in nhs:
+        if 16 % nh:
+            raise ValueError("nh must divide 16")
+        S = np.zeros((nz, b - a), dtype=np.float64)
+        for j in range(1, nh + 1):
+            c0, P = cols(16 * j // nh)
+            kj, _ = O.harmonic_indices(ks, izc, j, nh, izc)
+            _, izj = O.harmonic_indices(0, rows, j, nh, izc)
+            S += P[np.ix_(izj, kj - c0)]
+        out[nh] = S
+    return a, out
+
+
+def compare_band(gpu: np.ndarray, sums: dict, thr: dict, a: int, k0: int, k1: int) -> dict:
+    """Both directions of the candidate comparison restricted to the columns
+    [k0, k1): every oracle candidate there (threshold and 3x3 maximum of the
+    band's sums) must be a GPU candidate and every GPU candidate there an
+    oracle candidate, except at borderline cells; common candidates' sums
+    agree to 1e-4 max(S, nh).  sums: band_sums output starting at column a."""
+    import oracle as O
+    o = {}
+    for nh, S in sums.items():
+        for iz, kl in O.find_peaks(S, thr[nh]):
+            k = int(kl) + a
+            if k0 <= k < k1:
+                o[(nh, k, int(iz))] = float(S[iz, kl])
+    sel = (gpu["k"] >= k0) & (gpu["k"] < k1)
+    g = {(int(c["nharm"]), int(c["k"]), int(c["iz"])): float(c["power"]) for c in gpu[sel]}
+    missing, extra, border = [], [], 0
+    for key in set(o) ^ set(g):
+        nh, k, iz = key
+        if nh in sums and is_borderline(sums[nh], thr[nh], nh, iz, k - a):
+            border += 1
+        elif key in o:
+            missing.append(key)
+        else:
+            extra.append(key)
+    worst = 0.0
+    for key in set(g) & set(o):
+        worst = max(worst, abs(g[key] - o[key]) / (REL * max(o[key], key[0])))
+    return dict(ok=not missing and not extra and worst <= 1.0, missing=missing, extra=extra,
+                borderline=border, n_gpu=len(g), n_orc=len(o), common=len(set(g) & set(o)),
+                max_err_fraction=worst)
