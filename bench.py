@@ -162,17 +162,19 @@ C4_LENGTHS = (1 << 21, 1 << 22, 1 << 23)
 
 
 def bench_batched(fdas, bank, xs, per_call: int, host=None):
-    """64 distinct trials through fdas_search_batch in calls of per_call, the
-    series resident in HBM; with `host` (the same series in host memory) also
-    with each call's series first copied from page-locked host memory on the
-    same stream (PCIe included)."""
+    """64 distinct trials through fdas_search_batch, per_call trials per call
+    (64: one launch of the persistent kernel), the series resident in HBM;
+    with `host` (the same series in host memory) also with the series first
+    copied from page-locked host memory (PCIe included): calls of per_call / 2
+    trials, each call's copies overlapping the previous call's search on a
+    second stream."""
     import torch
     seg_b, tpb_b, tune_ms = fdas.autotune(bank, N, nharm_max=NHARM, sigma=SIGMA)
     log(f"batched: {len(xs)} trials, {per_call} per call, segment {seg_b}, {tpb_b} templates per block")
     planb = fdas.Plan(bank, N, seg_b, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb_b)
-    bcap = 1 << 20
+    bcap = 1 << 19
     bout = fdas.pinned_candidates(bcap * per_call)
-    planb.search_batch(xs[:per_call], caps=[bcap] * per_call, out=bout)  # captures the graphs
+    counts = [len(c) for c in planb.search_batch(xs[:per_call], caps=[bcap] * per_call, out=bout)]  # allocates
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(0, len(xs), per_call):
@@ -182,16 +184,17 @@ def bench_batched(fdas, bank, xs, per_call: int, host=None):
     tb = time.perf_counter() - t0
     h2d = None
     if host is not None:
-        # each call's series copied from page-locked host memory on a second
-        # stream (default priority), the next call's copies overlapping the
-        # current call's search; a buffer is refilled only after the search
-        # that read it has finished
+        # calls of half the trials; each call's series copied from page-locked
+        # host memory on a second stream (default priority), the next call's
+        # copies overlapping the current call's search; a buffer is refilled
+        # only after the search that read it has finished
+        hc = max(1, per_call // 2)
         staged = [torch.from_numpy(x).pin_memory() for x in host]  # new page-locked copies
-        bufs = [[torch.empty_like(xs[0]) for _ in range(per_call)] for _ in range(2)]
+        bufs = [[torch.empty_like(xs[0]) for _ in range(hc)] for _ in range(2)]
         main, side = torch.cuda.current_stream(), torch.cuda.Stream()
         loaded = [torch.cuda.Event(), torch.cuda.Event()]
         freed = [torch.cuda.Event(), torch.cuda.Event()]
-        chunks = [staged[i:i + per_call] for i in range(0, len(staged), per_call)]
+        chunks = [staged[i:i + hc] for i in range(0, len(staged), hc)]
 
         def load(ci):
             b = ci % 2
@@ -216,14 +219,17 @@ def bench_batched(fdas, bank, xs, per_call: int, host=None):
         torch.cuda.synchronize()
         th = time.perf_counter() - t0
         h2d = {"value": round(len(staged) / th, 3), "unit": "DM trials/s",
-               "ms_per_trial": round(1e3 * th / len(staged), 4),
-               "data": "the same 64 series copied from page-locked host memory, the next call's copies "
-                       "overlapping the current call on a second stream"}
+               "ms_per_trial": round(1e3 * th / len(staged), 4), "trials_per_call": hc,
+               "data": f"the same {len(staged)} series copied from page-locked host memory, {hc} per call, the "
+                       "next call's copies overlapping the current call on a second stream"}
         del staged, bufs
     planb.close()
     return {"value": round(len(xs) / tb, 3), "unit": "DM trials/s", "trials": len(xs),
             "h2d_included": h2d,
             "trials_per_call": per_call, "ms_per_trial": round(1e3 * tb / len(xs), 4),
+            "launch": "one persistent-kernel launch per call of up to 64 trials" if seg_b in (4096, 8192)
+                      else "per-trial graphs on two streams",
+            "candidates_per_trial": {"min": min(counts), "max": max(counts), "mean": round(sum(counts) / len(counts), 1)},
             "data": "64 distinct trials, seeds 1000-1063, 0-3 pulsars each, resident in HBM",
             "autotuned": {"segment": seg_b, "templates_per_block": tpb_b,
                           "segment_dft_plus_correlate_ms": round(tune_ms, 4)},
@@ -250,9 +256,12 @@ def _replay(fdas, srv, trace, ring, paced_speedup, inflight):
     """Submit the trace's requests (from the ring of host series) and collect
     results.  paced_speedup > 0: request i is submitted at t_arrival / speedup;
     else as soon as fewer than `inflight` are outstanding.  Returns
-    (wall seconds, latencies in s, candidates found)."""
+    (wall seconds, latencies in s, candidates found, and the records of the
+    first request with a pulsar of each length)."""
     import numpy as np
     lat, found = [], 0
+    keep = {}  # tag -> length, for the first pulsar request of each length
+    kept = {}
     t0 = time.perf_counter()
     nxt = 0
     done = 0
@@ -268,6 +277,8 @@ def _replay(fdas, srv, trace, ring, paced_speedup, inflight):
             n = e["nsamp"]
             if e["has_pulsar"]:
                 x = ring[n][0]
+                if n not in keep.values():
+                    keep[nxt] = n
             else:
                 x = ring[n][1 + slot[n] % (RING - 1)]
                 slot[n] += 1
@@ -279,7 +290,9 @@ def _replay(fdas, srv, trace, ring, paced_speedup, inflight):
         lat.append(r[3])
         found += r[2]
         done += 1
-    return time.perf_counter() - t0, np.asarray(lat), found
+        if r[0] in keep:
+            kept[keep[r[0]]] = r[1]
+    return time.perf_counter() - t0, np.asarray(lat), found, kept
 
 
 def bench_served(fdas, bank, ring, requests: int, paced: int, speedup: float):
@@ -292,7 +305,17 @@ def bench_served(fdas, bank, ring, requests: int, paced: int, speedup: float):
     srv.submit(ring[N][1], tag=1 << 40)  # warm the buffers of the longest length
     srv.poll(timeout_ms=120000)
     log(f"served: saturated replay of {len(trace)} requests")
-    ts, lat_s, found = _replay(fdas, srv, trace, ring, 0.0, inflight=8)
+    ts, lat_s, found, kept = _replay(fdas, srv, trace, ring, 0.0, inflight=8)
+    # each length's first pulsar request against the same series searched
+    # alone with fdas_search (whose candidates the GPU tests compare with
+    # the FP64 oracle at these sizes)
+    import torch
+    same = {}
+    for n, recs in sorted(kept.items()):
+        pl = fdas.Plan(bank, n, SEG, nharm_max=NHARM, sigma=SIGMA)
+        want, _ = pl.search(torch.from_numpy(ring[n][0]).cuda())
+        pl.close()
+        same[str(n)] = {"candidates": int(len(recs)), "equal_alone": bool(np.array_equal(recs, want))}
     mean_bytes = sum(path_bytes(e["nsamp"], bank.nz) for e in trace) / len(trace)
     out = {"value": round(len(trace) / ts, 3), "unit": "DM trials/s", "requests": len(trace),
            "path_roofline": path_roofline(mean_bytes, len(trace) / ts),
@@ -300,13 +323,14 @@ def bench_served(fdas, bank, ring, requests: int, paced: int, speedup: float):
            "arrival": "saturated: next request submitted while 8 are in flight; host series, PCIe included",
            "data": f"ring of {RING} seeded host series per length (one with a pulsar), recycled",
            "candidates": int(found),
+           "served_vs_alone": same,
            "latency_ms": {"p50": round(1e3 * float(np.percentile(lat_s, 50)), 2),
                           "p99": round(1e3 * float(np.percentile(lat_s, 99)), 2)},
            "realtime_need": {"value": round(6000 / 530.0, 3), "unit": "DM trials/s"}}
     if paced > 0:
         sub = trace[:paced]
         log(f"served: {len(sub)} requests paced at {speedup:g}x real time")
-        tp, lat_p, _ = _replay(fdas, srv, sub, ring, speedup, inflight=1 << 30)
+        tp, lat_p, _, _ = _replay(fdas, srv, sub, ring, speedup, inflight=1 << 30)
         out["paced"] = {"requests": len(sub), "speedup": speedup,
                         "offered_rate": round(speedup * 6000 / 530.0, 3), "unit": "DM trials/s",
                         "wall_s": round(tp, 3),
@@ -621,7 +645,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--batch", type=int, default=16, help="trials per fdas_search_batch call")
+    ap.add_argument("--batch", type=int, default=64, help="trials per fdas_search_batch call")
     ap.add_argument("--batch-trials", type=int, default=64, help="distinct trials in the batched run (0 = skip)")
     ap.add_argument("--served", type=int, default=6000, help="requests of the served trace replayed (0 = skip)")
     ap.add_argument("--paced", type=int, default=1000, help="requests replayed at their arrival times")

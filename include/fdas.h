@@ -265,22 +265,39 @@ fdas_status fdas_plan_search_counts(const fdas_plan_t *plan, int64_t *out3);
 /* Several float32 series, possibly of different power-of-two lengths
  * nsamp[i] <= the plan's nsamp, through the hot path (no plane is returned).
  * The work is ordered after what hip_stream holds when the call is made, and
- * hip_stream is ordered after it on return.  Internally consecutive trials
- * alternate between two library-owned streams and two work buffers of their
- * own, so that one trial's memory-bound harmonic sums overlap the next
- * trial's correlation; each trial's launches are captured once per length in
- * a HIP graph.  A batch leaves the buffers of fdas_search alone: the
+ * hip_stream is ordered after it on return.
+ * With the FFT correlator, segment length 4096 or 8192 and no half-bin plane,
+ * up to 64 trials at a time go through ONE launch of a persistent kernel (a
+ * longer batch takes one launch per 64): per trial the real DFT and block
+ * medians run first, then the persistent workgroups take tiles from a device
+ * work queue -- segment DFTs, correlation tiles (segment x template block),
+ * harmonic-sum screen, exact-sum and neighbour-test tiles -- each trial's
+ * next stage released by a per-trial completion counter, with consecutive
+ * trials' stages interleaved (Sec. 1: an observation yields thousands of
+ * independent series; Sec. 4 steps 2-7 for each).  The clears, front end,
+ * persistent launch and count copies are captured in one HIP graph per call;
+ * candidates are sorted per trial afterwards.  Device memory, allocated on
+ * the first such call and kept by the plan: per trial (up to 64) its
+ * spectrum, medians, segment spectra and candidate records; four plane /
+ * screening-code / list slots shared round-robin by the trials.
+ * Other plans: consecutive trials alternate between two library-owned
+ * streams and two work buffers, so that one trial's harmonic sums overlap the
+ * next trial's correlation, each trial's launches captured once per length
+ * in a HIP graph.
+ * Either way a batch leaves the buffers of fdas_search alone: the
  * inspection, interpolation, refinement and work-count calls keep describing
  * the plan's last fdas_search.  Trial i's candidates go to
  * cands_host + sum_{j<i} cap[j], count to ncands[i].  Returns the first error,
- * or OVERFLOW if any trial overflowed. */
+ * or OVERFLOW if any trial overflowed; DEVICE if a dependency wait inside the
+ * persistent kernel ran out (the plan is then unusable). */
 fdas_status fdas_search_batch(fdas_plan_t *plan, int32_t n, const float *const *series_dev,
                               const int64_t *nsamp, fdas_cand *cands_host, const int64_t *cap,
                               int64_t *ncands, void *hip_stream);
 
 /* Autotuner for many-trial use: times the segment DFTs plus the fused
- * correlation for every segment length in {2048, 4096, 8192} that is >= 4h
- * and templates per workgroup in {7, 13, 26}, on a seeded synthetic noise
+ * correlation for every segment length in {4096, 8192} (those of the
+ * persistent batch launch) that is >= 4h and templates per workgroup in
+ * {7, 13, 26}, on a seeded synthetic noise
  * series of nsamp samples, and returns the fastest (seg, templates per block)
  * and its time in ms.  cache_path (may be NULL) names a text file of earlier
  * results keyed by (GPU arch, nsamp, nz, h); a hit skips the measurement, a
@@ -362,10 +379,17 @@ fdas_status fdas_dft_c64(int32_t log2n, int32_t inverse, int64_t batch, const vo
 /* ------------------------------------------------------------------ server
  * Continuous-batching request loop on one GPU.  The bank and per-length
  * plans stay resident; requests (float32 host series, power-of-two lengths
- * up to max_nsamp) are copied on submit, admitted while their device bytes
- * fit hbm_budget (0 = 90% of free HBM at creation) and a slot is free, and run
- * concurrently, one stream per slot.  Each result is what fdas_search returns
- * for the same series alone. */
+ * up to max_nsamp) are copied on submit, admitted while a slot is free and
+ * their device bytes fit -- within hbm_budget bytes of work buffers, or, with
+ * hbm_budget 0, within the device's free HBM read (hipMemGetInfo) at the
+ * moment a new work buffer is needed, less a reserve of 512 MiB + 1% of the
+ * total -- and run concurrently, one stream per slot.  Work buffers are
+ * cached per length and reused; idle ones of other lengths are freed when a
+ * request does not fit.  A finished request's records are copied
+ * asynchronously into a page-locked buffer of the server's pool, so the
+ * scheduler never waits on a copy.  Each result is what fdas_search returns
+ * for the same series alone.  NOMEM if one request of max_nsamp does not fit
+ * the budget (or the free HBM) at creation. */
 fdas_status fdas_server_create(const fdas_bank *bank, int32_t seg, const fdas_opts *opts,
                                int64_t max_nsamp, size_t hbm_budget, int32_t max_slots,
                                fdas_server **out);

@@ -90,7 +90,8 @@ extern "C" fdas_status fdas_autotune(const fdas_bank *bank, int64_t nsamp, const
     int32_t best_seg = 0, best_tpb = 0;
     const int32_t tpbs[] = {7, 13, 26};
     std::vector<fdas_cand> cands(1);
-    for (int32_t seg = 2048; seg <= 8192; seg *= 2) {
+    // the segment lengths of the persistent batch launch
+    for (int32_t seg = 4096; seg <= 8192; seg *= 2) {
         if (seg < 4 * bank->h) continue;
         fdas_plan_t *p = nullptr;
         st = fdas_plan(bank, nsamp, seg, &o, &p);

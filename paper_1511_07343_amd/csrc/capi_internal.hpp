@@ -50,6 +50,11 @@ struct Workspace {
 
 }  // namespace fdas
 
+namespace fdas {
+struct PBatch;  // resources of the persistent batch launch (batch.cpp)
+void destroy_pbatch(PBatch *pb);
+}  // namespace fdas
+
 struct fdas_plan_s {
     fdas_opts opts{};
     double zmax = 0.0, dz = 1.0;
@@ -77,6 +82,8 @@ struct fdas_plan_s {
     std::array<hipEvent_t, 4> events{};
     // batched path: captured per-trial launch sequence, per slot and length
     std::array<std::map<int64_t, hipGraphExec_t>, 2> graphs{};
+    // persistent batch launch (one launch per up to 64 trials)
+    fdas::PBatch *pbatch = nullptr;
     bool broken = false;
     // fdas_search_host: two device input buffers filled on a copy stream of
     // the plan's own; the host pointer whose copy into in_dev[staged_slot]

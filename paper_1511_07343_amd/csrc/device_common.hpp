@@ -37,12 +37,12 @@ __device__ __forceinline__ uint8_t power_code(float pw, float code_inv) {
     return uint8_t(fminf(ceilf(pw * code_inv), 255.f));
 }
 
-// Code of a 2-bin block: the larger of its bins' codes (255 if either is NaN,
-// which fmaxf alone would drop).
+// Code of a 2-bin block: the larger of its bins' codes, 255 if either is NaN.
+// Powers are non-negative (or NaN), and non-negative floats, with NaN above
+// +inf, order as their unsigned bit patterns, so one integer maximum picks
+// the larger power and keeps a NaN (fmaxf alone would drop it).
 __device__ __forceinline__ uint8_t block_code(float a, float b, float code_inv) {
-    float m = fmaxf(a, b);
-    const float sum = a + b;
-    if (!(sum == sum)) m = INFINITY;
+    const float m = __uint_as_float(max(__float_as_uint(a), __float_as_uint(b)));
     return uint8_t(fminf(ceilf(m * code_inv), 255.f));
 }
 

@@ -706,6 +706,8 @@ void fdas_plan_destroy(fdas_plan_t *plan) {
     }
     for (auto &m : plan->graphs)
         for (auto &kv : m) (void)hipGraphExecDestroy(kv.second);
+    destroy_pbatch(plan->pbatch);
+    plan->pbatch = nullptr;
     if (plan->d_bank) (void)hipFree(plan->d_bank);
     if (plan->d_bank_half) (void)hipFree(plan->d_bank_half);
     if (plan->d_gemm) (void)hipFree(plan->d_gemm);

@@ -19,8 +19,11 @@ constexpr int fft_threads(int log2s) {
     return log2s >= 12 ? 256 : log2s == 11 ? 128 : log2s >= 8 ? 64 : 32;
 }
 
-// Threads per workgroup of the fused correlation kernel.
+// Threads per workgroup of the fused correlation kernel, and the waves per
+// SIMD its register budget is held to (4096 points on the integer grid fit
+// 128 registers).
 constexpr int corr_threads(int log2s) { return fft_threads(log2s); }
+constexpr int corr_waves(int log2s, bool interbin) { return log2s == 12 && !interbin ? 4 : 2; }
 
 // 8 XCDs on MI355X; workgroups are dispatched to XCDs round-robin by index.
 constexpr int kXcds = 8;
@@ -28,6 +31,25 @@ constexpr int kXcds = 8;
 // Plane stores bypass the L2 retention (streaming), so that they do not evict
 // the templates an XCD reuses across segments.
 typedef float f32x4v __attribute__((ext_vector_type(4)));
+
+// Raw buffer access (gfx950 buffer instructions): a resource with a 64-bit
+// base and a byte extent, a 32-bit lane offset and a wave-uniform constant
+// offset.  Accesses past the extent read 0 / are dropped.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), short(0), bytes, 0x00020000);
+}
+// element (lane + k) of a float2 array
+__device__ __forceinline__ float2 buffer_load_f2(__amdgpu_buffer_rsrc_t r, int lane, int k) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, lane * 8, k * 8, 0));
+}
+typedef unsigned u32x4v __attribute__((ext_vector_type(4)));
+constexpr int kCachePolicyNT = 2;  // non-temporal (streaming) store
+__device__ __forceinline__ void buffer_store_nt_f4(float4 v, __amdgpu_buffer_rsrc_t r, int byte_off) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4v, v), r, byte_off, 0, kCachePolicyNT);
+}
+__device__ __forceinline__ void buffer_store_nt_u16(uint16_t v, __amdgpu_buffer_rsrc_t r, int byte_off) {
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, byte_off, 0, kCachePolicyNT);
+}
 
 // Valid points per segment: S - 2h rounded down to a multiple of 4, so that
 // the correlation's 4-bin store chunks (and the 2-bin blocks of the screening
@@ -320,15 +342,13 @@ __global__ __launch_bounds__(kMedThreads) void k_median(const float2 *__restrict
 }
 
 // -------------------------------------------------------- segment DFTs
+// Segment s (one workgroup of fft_threads(LOG2S) threads, lds holding
+// FftShape::LDS_FLOAT2 float2): DFT of Xhat[s L - h + n], n in [0, S).
 template <int LOG2S>
-__global__ __launch_bounds__(fft_threads(LOG2S)) void k_segfft(const float2 *__restrict__ X,
-                                                               const double *__restrict__ med,
-                                                               int W, int64_t nb, int h,
-                                                               float2 *__restrict__ segspec) {
+__device__ __forceinline__ void segfft_item(float2 *lds, int t, const float2 *__restrict__ X,
+                                            const double *__restrict__ med, int W, int64_t nb, int h, int64_t s,
+                                            float2 *__restrict__ segspec) {
     using Sh = FftShape<LOG2S, fft_threads(LOG2S)>;
-    __shared__ float2 lds[Sh::LDS_FLOAT2];
-    const int t = threadIdx.x;
-    const int64_t s = blockIdx.x;
     const int64_t L = seg_valid(Sh::S, h);
     const int64_t g0 = s * L - h;
     const int64_t nblk = (nb + W - 1) / W;
@@ -352,6 +372,16 @@ __global__ __launch_bounds__(fft_threads(LOG2S)) void k_segfft(const float2 *__r
     fft_wg<Sh, -1>(v, lds, tw, t);
 #pragma unroll
     for (int m = 0; m < Sh::R; ++m) segspec[s * Sh::S + t + Sh::NT * m] = v[m];
+}
+
+template <int LOG2S>
+__global__ __launch_bounds__(fft_threads(LOG2S)) void k_segfft(const float2 *__restrict__ X,
+                                                               const double *__restrict__ med,
+                                                               int W, int64_t nb, int h,
+                                                               float2 *__restrict__ segspec) {
+    using Sh = FftShape<LOG2S, fft_threads(LOG2S)>;
+    __shared__ float2 lds[Sh::LDS_FLOAT2];
+    segfft_item<LOG2S>(lds, threadIdx.x, X, med, W, nb, h, blockIdx.x, segspec);
 }
 
 // Xhat = X sqrt(ln2 / m(k)) written out (inspection only; the search path
@@ -381,30 +411,23 @@ __global__ __launch_bounds__(256) void k_normalise(const float2 *__restrict__ X,
 // pass stores the codes of its own 4 points (one byte each); the second pass
 // (same thread, same chunk) reads that word back and keeps the larger code
 // of each pair.
+// Work item (segment s, template block tb): templates [tb tpb, min(nz, (tb + 1) tpb)).
 template <int LOG2S, bool INTERBIN>
-__global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
-    const float2 *__restrict__ segspec, const float2 *__restrict__ bank, const float2 *__restrict__ bank_half,
-    int nz, int tpb, int64_t nb, int h, int64_t nseg, int64_t total, int64_t per, int grp,
-    float *__restrict__ plane, uint8_t *__restrict__ codes, float code_inv) {
+__device__ __forceinline__ void correlate_item(float2 *lds, const Twiddles<FftShape<LOG2S, corr_threads(LOG2S)>, +1> &tw,
+                                               int t, const float2 *__restrict__ segspec,
+                                               const float2 *__restrict__ bank, const float2 *__restrict__ bank_half,
+                                               int nz, int tpb, int64_t nb, int h, int64_t s, int64_t tb,
+                                               float *__restrict__ plane, uint8_t *__restrict__ codes,
+                                               float code_inv) {
     using Sh = FftShape<LOG2S, corr_threads(LOG2S)>;
-    __shared__ float2 lds[Sh::LDS_FLOAT2];
-    const int t = threadIdx.x;
-    const int64_t u = int64_t(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
-    if (u >= total) return;
-    const int64_t gsz = int64_t(grp) * nseg;
-    const int64_t gi = u / gsz;
-    const int64_t gr = u - gi * gsz;
-    const int64_t s = gr / grp;
-    const int64_t tb = gi * grp + (gr - s * grp);
     const int64_t L = seg_valid(Sh::S, h);
     const int iz0 = int(tb) * tpb;
     const int iz1 = min(nz, iz0 + tpb);
-
-    Twiddles<Sh, +1> tw;
-    tw.init(t);
     // The segment spectrum is re-read per template (from L2: consecutive
     // workgroups of an XCD share it); keeping it in registers would spill.
-    const float2 *__restrict__ sp = segspec + s * Sh::S;
+    // Operands come through buffer loads: one 32-bit lane offset and a
+    // per-point constant offset, no 64-bit address arithmetic per load.
+    const __amdgpu_buffer_rsrc_t rsp = buffer_rsrc(segspec + s * Sh::S, Sh::S * 8);
 
     const int64_t kbase = s * L - h;  // plane column of segment point n is kbase + n
     // points [h, nend) of this segment are plane columns [s L, min(s L + L, nb))
@@ -414,17 +437,16 @@ __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
     for (int it = iz0 * PASSES; it < iz1 * PASSES; ++it) {
         const int iz = INTERBIN ? (it >> 1) : it;
         const bool second = INTERBIN && (it & 1);
-        // Keep the per-point offsets inside the loop: hoisting the 32 addresses
-        // of each operand out of it would cost more registers than recomputing.
+        // Keep the lane offset inside the loop: hoisting the per-point
+        // addresses out of it would cost more registers than recomputing.
         int to = t;
         asm volatile("" : "+v"(to));
-        const float2 *__restrict__ bz = (second ? bank_half : bank) + int64_t(iz) * Sh::S;
+        const __amdgpu_buffer_rsrc_t rbz = buffer_rsrc((second ? bank_half : bank) + int64_t(iz) * Sh::S, Sh::S * 8);
         float2 v[Sh::R];
 #pragma unroll
-        for (int m = 0; m < Sh::R; ++m) v[m] = cmul(sp[to + Sh::NT * m], bz[to + Sh::NT * m]);
+        for (int m = 0; m < Sh::R; ++m)
+            v[m] = cmul(buffer_load_f2(rsp, to, Sh::NT * m), buffer_load_f2(rbz, to, Sh::NT * m));
         fft_wg<Sh, +1>(v, lds, tw, t);
-        float *__restrict__ row = plane + int64_t(iz) * nb * PASSES + (second ? nb : 0) + kbase;
-        uint8_t *__restrict__ qrow = codes + int64_t(iz) * (nb * PASSES / 2);
         // Powers through LDS so that each thread stores 4 consecutive
         // points: point n sits at LDS index n + sh, which puts chunk c
         // (indices 4c .. 4c+3) on a 16-byte boundary of the plane row, i.e.
@@ -435,15 +457,39 @@ __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
         for (int m = 0; m < Sh::R; ++m) lf[sh + to + Sh::NT * m] = cnorm(v[m]);
         __syncthreads();
         constexpr int NCH = (Sh::S + 6) / 4;  // chunks covering indices [0, S + 3)
-        for (int c = t; c < NCH; c += Sh::NT) {
-            const int n0 = 4 * c - sh;
-            const float4 p4 = *reinterpret_cast<const float4 *>(lf + 4 * c);
-            if (n0 >= h && n0 + 4 <= nend) {
-                __builtin_nontemporal_store(__builtin_bit_cast(f32x4v, p4), reinterpret_cast<f32x4v *>(row + n0));
-                if constexpr (!INTERBIN) {
-                    __builtin_nontemporal_store(block_codes4(p4, code_inv),
-                                                reinterpret_cast<uint16_t *>(qrow + ((kbase + n0) >> 1)));
-                } else {
+        if constexpr (!INTERBIN) {
+            // Chunk c holds plane columns kbase - sh + 4c .. + 3 and the codes
+            // of blocks (kbase - sh) / 2 + 2c, + 1 (kbase - sh is a multiple
+            // of 4).  Per-row buffer resources bound the stores to the kept
+            // points; three chunks per step so that their LDS reads overlap.
+            float *__restrict__ row = plane + int64_t(iz) * nb + kbase;
+            uint8_t *__restrict__ qrow = codes + int64_t(iz) * (nb / 2) + (kbase - sh) / 2;
+            const __amdgpu_buffer_rsrc_t rrow = buffer_rsrc(row, nend * 4);
+            const __amdgpu_buffer_rsrc_t rq = buffer_rsrc(qrow, (nend + sh) / 2);
+            constexpr int UNR = 3;
+            for (int c0 = t; c0 < NCH; c0 += UNR * Sh::NT) {
+                float4 p4[UNR];
+#pragma unroll
+                for (int k = 0; k < UNR; ++k)
+                    p4[k] = *reinterpret_cast<const float4 *>(lf + 4 * min(c0 + k * Sh::NT, NCH - 1));
+#pragma unroll
+                for (int k = 0; k < UNR; ++k) {
+                    const int c = c0 + k * Sh::NT;
+                    const int n0 = 4 * c - sh;
+                    if (c < NCH && n0 >= h && n0 + 4 <= nend) {
+                        buffer_store_nt_f4(p4[k], rrow, 4 * n0);
+                        buffer_store_nt_u16(block_codes4(p4[k], code_inv), rq, 2 * c);
+                    }
+                }
+            }
+        } else {
+            float *__restrict__ row = plane + int64_t(iz) * nb * PASSES + (second ? nb : 0) + kbase;
+            uint8_t *__restrict__ qrow = codes + int64_t(iz) * (nb * PASSES / 2);
+            for (int c = t; c < NCH; c += Sh::NT) {
+                const int n0 = 4 * c - sh;
+                const float4 p4 = *reinterpret_cast<const float4 *>(lf + 4 * c);
+                if (n0 >= h && n0 + 4 <= nend) {
+                    __builtin_nontemporal_store(__builtin_bit_cast(f32x4v, p4), reinterpret_cast<f32x4v *>(row + n0));
                     uint32_t q = uint32_t(power_code(p4.x, code_inv)) | (uint32_t(power_code(p4.y, code_inv)) << 8) |
                                  (uint32_t(power_code(p4.z, code_inv)) << 16) |
                                  (uint32_t(power_code(p4.w, code_inv)) << 24);
@@ -462,6 +508,27 @@ __global__ __launch_bounds__(corr_threads(LOG2S), 2) void k_correlate(
         }
         __syncthreads();  // the next transform writes lds
     }
+}
+
+template <int LOG2S, bool INTERBIN>
+__global__ __launch_bounds__(corr_threads(LOG2S), corr_waves(LOG2S, INTERBIN)) void k_correlate(
+    const float2 *__restrict__ segspec, const float2 *__restrict__ bank, const float2 *__restrict__ bank_half,
+    int nz, int tpb, int64_t nb, int h, int64_t nseg, int64_t total, int64_t per, int grp,
+    float *__restrict__ plane, uint8_t *__restrict__ codes, float code_inv) {
+    using Sh = FftShape<LOG2S, corr_threads(LOG2S)>;
+    __shared__ float2 lds[Sh::LDS_FLOAT2];
+    const int t = threadIdx.x;
+    const int64_t u = int64_t(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    if (u >= total) return;
+    const int64_t gsz = int64_t(grp) * nseg;
+    const int64_t gi = u / gsz;
+    const int64_t gr = u - gi * gsz;
+    const int64_t s = gr / grp;
+    const int64_t tb = gi * grp + (gr - s * grp);
+    Twiddles<Sh, +1> tw;
+    tw.init(t);
+    correlate_item<LOG2S, INTERBIN>(lds, tw, t, segspec, bank, bank_half, nz, tpb, nb, h, s, tb, plane, codes,
+                                    code_inv);
 }
 
 // ------------------------------------------------ harmonic sum and peaks
@@ -641,25 +708,26 @@ __device__ __forceinline__ uint32_t wave_scan(uint32_t x, int lane) {
     return x;
 }
 
+// Screen tile (bx, by) of a workgroup of 64 SC_WAVES threads: columns
+// [bx SC_WAVES 2048, + SC_WAVES 2048), rows [by SC_TZ, + SC_TZ).  rowmask_lds:
+// SC_WAVES SC_TZ 64 words of LDS.
 template <int LEVELS>
-__global__ __launch_bounds__(64 * SC_WAVES) void k_screen(const uint8_t *__restrict__ Q, int nz, int64_t nb,
-                                                          int izc, ScreenThr T, Group *__restrict__ groups,
-                                                          uint2 *__restrict__ blocks, uint32_t *__restrict__ group_map,
-                                                          uint32_t *__restrict__ cnt, uint32_t group_cap,
-                                                          uint32_t cell_cap) {
-    // Row masks of the wave, kept until its records are written.
-    __shared__ uint32_t rowmask_lds[SC_WAVES][SC_TZ][64];
+__device__ __forceinline__ void screen_tile(uint32_t *rowmask_lds, int64_t bx, int by, const uint8_t *__restrict__ Q,
+                                            int nz, int64_t nb, int izc, const ScreenThr &T,
+                                            Group *__restrict__ groups, uint2 *__restrict__ blocks,
+                                            uint32_t *__restrict__ group_map, uint32_t *__restrict__ cnt,
+                                            uint32_t group_cap, uint32_t cell_cap) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     // a workgroup covers SC_WAVES * 2048 columns and SC_TZ rows
-    const int64_t m = (int64_t(blockIdx.x) * SC_WAVES + wave) * 64 + lane;  // column group
-    const int iz0 = blockIdx.y * SC_TZ;
+    const int64_t m = (bx * SC_WAVES + wave) * 64 + lane;  // column group
+    const int iz0 = by * SC_TZ;
     const int64_t ngr = nb / SC_COLS;
     const int64_t qlen = nb / 2;  // codes per row
     const bool valid = m < ngr;
     if (!__any(valid) || iz0 >= nz) return;
     const int64_t mm = valid ? m : 0;  // lanes past the end read group 0 and report nothing
-    uint32_t *__restrict__ rowmask = &rowmask_lds[wave][0][lane];  // row r at rowmask[64 r]
+    uint32_t *__restrict__ rowmask = rowmask_lds + wave * (SC_TZ * 64) + lane;  // row r at rowmask[64 r]
     uint32_t mycells = 0, mygroups = 0;
 #pragma unroll 1
     for (int r = 0; r < SC_TZ; ++r) {
@@ -738,6 +806,18 @@ __global__ __launch_bounds__(64 * SC_WAVES) void k_screen(const uint8_t *__restr
     }
 }
 
+template <int LEVELS>
+__global__ __launch_bounds__(64 * SC_WAVES) void k_screen(const uint8_t *__restrict__ Q, int nz, int64_t nb,
+                                                          int izc, ScreenThr T, Group *__restrict__ groups,
+                                                          uint2 *__restrict__ blocks, uint32_t *__restrict__ group_map,
+                                                          uint32_t *__restrict__ cnt, uint32_t group_cap,
+                                                          uint32_t cell_cap) {
+    // Row masks of the waves, kept until their records are written.
+    __shared__ uint32_t rowmask_lds[SC_WAVES * SC_TZ * 64];
+    screen_tile<LEVELS>(rowmask_lds, blockIdx.x, blockIdx.y, Q, nz, nb, izc, T, groups, blocks, group_map, cnt,
+                        group_cap, cell_cap);
+}
+
 constexpr int SUM_STRIDE = 5;  // floats per flagged cell in the sums array
 
 // Cell index of bin i (< 32) of a group, when its block is flagged.
@@ -753,8 +833,10 @@ __device__ __forceinline__ uint32_t cell_index(const Group &r, int i) {
 // cells per step) so that one atomic per step reserves the hit slots of its
 // four waves: with one atomic per wave the counter's contention made a trial
 // with strong pulsars 30 % slower.
+// Exact-sum workgroup wg of nwg (256 threads): flagged cells wg 256 + i,
+// stepping by nwg 256.
 template <int LEVELS>
-__global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int nz, int64_t nb, int64_t split,
+__device__ __forceinline__ void exact_tile(uint32_t wg, uint32_t nwg, const float *__restrict__ P, int nz, int64_t nb, int64_t split,
                                                int izc, Thr thr,
                                                const uint2 *__restrict__ blocks, uint32_t *__restrict__ cnt,
                                                uint32_t cell_cap, float *__restrict__ sums,
@@ -764,9 +846,9 @@ __global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int 
     const uint32_t nc = min(cell_count(cnt), cell_cap);
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t stride = nwg * 256u;
     // the bounds of this loop are the same for every thread of the workgroup
-    for (uint32_t base = blockIdx.x * blockDim.x; base < nc; base += stride) {
+    for (uint32_t base = wg * 256u; base < nc; base += stride) {
         const uint32_t c = base + threadIdx.x;
         bool hit = false;
         if (c < nc) {
@@ -801,6 +883,15 @@ __global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int 
     }
 }
 
+template <int LEVELS>
+__global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int nz, int64_t nb, int64_t split,
+                                               int izc, Thr thr,
+                                               const uint2 *__restrict__ blocks, uint32_t *__restrict__ cnt,
+                                               uint32_t cell_cap, float *__restrict__ sums,
+                                               uint32_t *__restrict__ hits) {
+    exact_tile<LEVELS>(blockIdx.x, gridDim.x, P, nz, nb, split, izc, thr, blocks, cnt, cell_cap, sums, hits);
+}
+
 // Pass 3, one lane per hit: the 3x3 local maximum at every level the cell
 // reaches.  A cell keeps a level when it is strictly greater than the
 // neighbours earlier in row-major (iz, k) order and at least equal to the
@@ -808,8 +899,10 @@ __global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int 
 // not flagged has sums below every threshold, hence below the cell's, and is
 // beaten without being looked at; the others are found through the group map
 // (map entry, record, sums, issued side by side for the 8 neighbours).
+// Neighbour-test workgroup wg of nwg (256 threads): hits wg 256 + i,
+// stepping by nwg 256.
 template <int LEVELS>
-__global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, const Group *__restrict__ groups,
+__device__ __forceinline__ void peaks_tile(uint32_t wg, uint32_t nwg, int nz, int64_t nb, Thr thr, const Group *__restrict__ groups,
                                                const uint32_t *__restrict__ group_map, const uint2 *__restrict__ blocks,
                                                const float *__restrict__ sums, const uint32_t *__restrict__ hits,
                                                uint32_t *__restrict__ cnt, uint32_t group_cap, uint32_t cell_cap,
@@ -824,7 +917,7 @@ __global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, cons
     // the workgroup iterates as a whole (256 hits per step) so that one
     // atomic per step reserves the slots of all its candidates
     int par = 0;
-    for (uint32_t hw = blockIdx.x * blockDim.x; hw < nh; hw += gridDim.x * blockDim.x, par ^= 1) {
+    for (uint32_t hw = wg * 256u; hw < nh; hw += nwg * 256u, par ^= 1) {
         const uint32_t hidx = hw + threadIdx.x;
         uint32_t lmask = 0;  // levels still alive
         int64_t k = 0;
@@ -911,9 +1004,211 @@ __global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, cons
     }
 }
 
+template <int LEVELS>
+__global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, const Group *__restrict__ groups,
+                                               const uint32_t *__restrict__ group_map, const uint2 *__restrict__ blocks,
+                                               const float *__restrict__ sums, const uint32_t *__restrict__ hits,
+                                               uint32_t *__restrict__ cnt, uint32_t group_cap, uint32_t cell_cap,
+                                               DevCand *__restrict__ cands, uint32_t cap) {
+    peaks_tile<LEVELS>(blockIdx.x, gridDim.x, nz, nb, thr, groups, group_map, blocks, sums, hits, cnt, group_cap, cell_cap, cands, cap);
+}
+
 __global__ void k_zero_u32(uint32_t *__restrict__ p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
+}
+
+
+// ------------------------------------------------- persistent batch kernel
+// Scratch layout of the harmonic-sum passes (launch_harmsum's order).
+struct HarmLists {
+    Group *groups;
+    float *sums;
+    uint2 *blocks;
+    uint32_t *hits;
+    uint32_t *group_map;
+};
+__device__ __forceinline__ HarmLists harm_lists(void *scratch, uint32_t cell_cap, uint32_t group_cap) {
+    HarmLists r;
+    r.groups = static_cast<Group *>(scratch);
+    r.sums = reinterpret_cast<float *>(r.groups + group_cap);
+    r.blocks = reinterpret_cast<uint2 *>(r.sums + size_t(cell_cap) * SUM_STRIDE);
+    r.hits = reinterpret_cast<uint32_t *>(r.blocks + cell_cap / 2);
+    r.group_map = r.hits + cell_cap;
+    return r;
+}
+
+struct BatchArgs {
+    const BatchTrial *trials;
+    const uint32_t *tiles;
+    uint32_t *ctl;
+    const float2 *bank;
+    int ntrials, slots, nz, tpb, h, W, izc;
+    uint32_t ntiles, cell_cap, group_cap, cand_cap;
+    float code_inv;
+    Thr thr;
+    ScreenThr T;
+};
+
+// A dependency wait gives up after this long (device wall clock, 100 MHz
+// ticks: 1 s), orders of magnitude above the longest legitimate wait (one
+// trial's correlation), and raises the error flag.  Bounded in time, not in
+// polls: under contention one poll can take long.
+constexpr uint64_t kBatchWaitTicks = 100000000ull;
+
+// Counter value as the device's coherence point holds it: an atomic add of
+// zero (a read-modify-write is performed where every XCD's atomics are,
+// which a plain load need not see at once).
+__device__ __forceinline__ uint32_t coherent_read(uint32_t *p) {
+    return __hip_atomic_fetch_add(p, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Executed by all lanes of one wave together (the loop condition is
+// wave-uniform).  Waits until *done >= target, then one acquire fence at
+// agent scope so that the producers' results are visible to the whole
+// workgroup after its next barrier.  False when the error flag is raised, by
+// this wait running out (which records what it waited for in ctl[2..5]) or by
+// another workgroup's.
+__device__ __forceinline__ bool batch_wait(uint32_t *done, uint32_t target, uint32_t *ctl, uint32_t stage,
+                                           uint32_t trial) {
+    const uint64_t t0 = wall_clock64();
+    for (uint32_t it = 0;; ++it) {
+        const uint32_t v = __builtin_amdgcn_readfirstlane(coherent_read(done));
+        if (v >= target) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return true;
+        }
+        if ((it & 15u) == 15u) {
+            if (__builtin_amdgcn_readfirstlane(coherent_read(ctl + 1)) != 0u) return false;
+            if (wall_clock64() - t0 > kBatchWaitTicks) {
+                uint32_t first = 1u;
+                if (threadIdx.x == 0) first = atomicCAS(ctl + 1, 0u, 1u);
+                if (__builtin_amdgcn_readfirstlane(first) == 0u && threadIdx.x == 0) {
+                    ctl[2] = stage;
+                    ctl[3] = trial;
+                    ctl[4] = v;
+                    ctl[5] = target;
+                }
+                return false;
+            }
+        }
+        __builtin_amdgcn_s_sleep(32);
+    }
+}
+
+// Workgroups take tiles of the global order from ctl[0]; see
+// launch_batch_persistent.  Correlation tiles of a trial walk its segments
+// template block by template block, so that every XCD keeps one block's
+// templates in its L2 while the segment spectra stream past.
+template <int LOG2S, int LEVELS>
+__global__ __launch_bounds__(256, 2) void k_batch(BatchArgs a) {
+    using Sh = FftShape<LOG2S, 256>;
+    static_assert(corr_threads(LOG2S) == 256 && fft_threads(LOG2S) == 256, "256-thread transforms");
+    static_assert(SC_WAVES * 64 == 256, "screen tiles of 256 threads");
+    static_assert(Sh::LDS_FLOAT2 * 2 >= SC_WAVES * SC_TZ * 64, "screen masks fit the transform buffer");
+    __shared__ float2 lds[Sh::LDS_FLOAT2];
+    __shared__ uint32_t tinfo[3];
+    const int t = threadIdx.x;
+    uint32_t *const err = a.ctl + 1;
+    uint32_t *const done = a.ctl + kBatchCtlHead;
+    const int n = a.ntrials;
+    // Wave 0 (all its lanes, under a wave-uniform branch) completes the
+    // previous tile and takes the next one; no lane-divergent region holds a
+    // barrier or spans the loop's back edge, so every wave runs the same
+    // sequence of barriers.
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(uint32_t(threadIdx.x) >> 6);
+    uint32_t prev_stage = BST_N, prev_trial = 0;
+    for (;;) {
+        if (wave == 0) {
+            if (prev_stage < BST_N) {  // release the previous tile
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                // the L2 write-back has completed before the count moves
+                // (the fence's own wait can be dropped as redundant when no
+                // store is outstanding)
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                if (t == 0)
+                    __hip_atomic_fetch_add(done + prev_stage * n + prev_trial, 1u, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            }
+            uint32_t stage = BST_N, trial = 0, idx = 0;
+            if (__builtin_amdgcn_readfirstlane(coherent_read(err)) == 0u) {
+                uint32_t tile = 0;
+                if (t == 0) tile = atomicAdd(a.ctl, 1u);
+                tile = __builtin_amdgcn_readfirstlane(tile);
+                if (tile < a.ntiles) {
+                    const uint32_t w = __builtin_amdgcn_readfirstlane(a.tiles[tile]);
+                    stage = w >> 29;
+                    trial = (w >> 23) & 63u;
+                    idx = w & (kBatchMaxStageTiles - 1u);
+                    const BatchTrial *tr = a.trials;
+                    bool ok = stage < BST_N && int(trial) < n && idx < tr[trial].ntile[stage];
+                    if (!ok) {
+                        if (t == 0) atomicCAS(err, 0u, 2u);  // malformed order
+                    } else if (stage == BST_CORR) {
+                        ok = batch_wait(done + BST_SEG * n + trial, tr[trial].ntile[BST_SEG], a.ctl, BST_SEG, trial);
+                        if (ok && int(trial) >= a.slots) {
+                            const uint32_t prev = trial - uint32_t(a.slots);  // the slot's last user
+                            ok = batch_wait(done + BST_PEAK * n + prev, tr[prev].ntile[BST_PEAK], a.ctl, BST_PEAK,
+                                            prev);
+                        }
+                    } else if (stage != BST_SEG) {
+                        ok = batch_wait(done + (stage - 1) * n + trial, tr[trial].ntile[stage - 1], a.ctl, stage - 1,
+                                        trial);
+                    }
+                    if (!ok) stage = BST_N;
+                }
+            }
+            if (t == 0) {
+                tinfo[0] = stage;
+                tinfo[1] = trial;
+                tinfo[2] = idx;
+            }
+        }
+        __syncthreads();
+        // workgroup-uniform: in scalar registers, so that the trial's
+        // descriptor is read with scalar loads
+        const uint32_t stage = __builtin_amdgcn_readfirstlane(tinfo[0]);
+        const uint32_t trial = __builtin_amdgcn_readfirstlane(tinfo[1]);
+        const uint32_t idx = __builtin_amdgcn_readfirstlane(tinfo[2]);
+        if (stage >= BST_N) break;
+        const BatchTrial &tr = a.trials[trial];
+        // The thread index made opaque per tile, so that the twiddles of the
+        // transform tiles are computed per tile instead of being hoisted out
+        // of the loop (both directions' tables held across every tile would
+        // not fit the register file).
+        int to = t;
+        asm volatile("" : "+v"(to));
+        if (stage == BST_SEG) {
+            segfft_item<LOG2S>(lds, to, tr.X, tr.med, a.W, tr.nb, a.h, int64_t(idx), tr.seg);
+        } else if (stage == BST_CORR) {
+            const int64_t s = int64_t(idx) % tr.nseg, tb = int64_t(idx) / tr.nseg;
+            Twiddles<Sh, +1> tw;
+            tw.init(to);
+            correlate_item<LOG2S, false>(lds, tw, to, tr.seg, a.bank, nullptr, a.nz, a.tpb, tr.nb, a.h, s, tb, tr.plane,
+                                         tr.codes, a.code_inv);
+        } else {
+            const HarmLists hl = harm_lists(tr.hits, a.cell_cap, a.group_cap);
+            if (stage == BST_SCREEN) {
+                const int64_t ncolt = (tr.nb + int64_t(SC_WAVE_COLS) * SC_WAVES - 1) / (int64_t(SC_WAVE_COLS) * SC_WAVES);
+                screen_tile<LEVELS>(reinterpret_cast<uint32_t *>(lds), int64_t(idx) % ncolt, int(int64_t(idx) / ncolt),
+                                    tr.codes, a.nz, tr.nb, a.izc, a.T, hl.groups, hl.blocks, hl.group_map, tr.cnt,
+                                    a.group_cap, a.cell_cap);
+            } else if (stage == BST_EXACT) {
+                exact_tile<LEVELS>(idx, kBatchExactTiles, tr.plane, a.nz, tr.nb, 0, a.izc, a.thr, hl.blocks, tr.cnt,
+                                   a.cell_cap, hl.sums, hl.hits);
+            } else {
+                peaks_tile<LEVELS>(idx, kBatchPeakTiles, a.nz, tr.nb, a.thr, hl.groups, hl.group_map, hl.blocks,
+                                   hl.sums, hl.hits, tr.cnt, a.group_cap, a.cell_cap, tr.cands, a.cand_cap);
+            }
+        }
+        // Every wave's stores have reached the L2 before thread 0 releases
+        // the tile at the top of the next iteration (the release writes the
+        // L2 back for the other XCDs).
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        prev_stage = stage;
+        prev_trial = trial;
+    }
 }
 
 // ------------------------------------------------------------ dispatch
@@ -1102,6 +1397,72 @@ hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int6
         case 3: CALL(3); break;
         default: CALL(4); break;
     }
+#undef CALL
+    return hipGetLastError();
+}
+
+
+uint32_t batch_screen_tiles(int64_t nb, int nz) {
+    const int64_t cols = int64_t(SC_WAVE_COLS) * SC_WAVES;
+    return uint32_t(((nb + cols - 1) / cols) * ((nz + SC_TZ - 1) / SC_TZ));
+}
+
+static int harm_levels(int nharm_max) {
+    int levels = 0;
+    while ((1 << levels) < nharm_max) ++levels;
+    return (1 << levels) == nharm_max && levels <= 4 ? levels : -1;
+}
+
+hipError_t batch_persistent_workgroups(int log2s, int nharm_max, int *per_cu) {
+    const int levels = harm_levels(nharm_max);
+    if (levels < 0 || (log2s != 12 && log2s != 13)) return hipErrorInvalidValue;
+    hipError_t e = hipErrorInvalidValue;
+#define OCC(LS, LV)                                                                                         \
+    if (log2s == LS && levels == LV)                                                                        \
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, reinterpret_cast<const void *>(&k_batch<LS, LV>), \
+                                                         256, 0);
+    OCC(12, 0) OCC(12, 1) OCC(12, 2) OCC(12, 3) OCC(12, 4)
+    OCC(13, 0) OCC(13, 1) OCC(13, 2) OCC(13, 3) OCC(13, 4)
+#undef OCC
+    return e;
+}
+
+hipError_t launch_batch_persistent(int log2s, int nharm_max, const BatchTrial *trials, int ntrials,
+                                   const uint32_t *tiles, uint32_t ntiles, uint32_t *ctl, int slots,
+                                   const float2 *bank, int nz, int tpb, int h, int W, int izc, float code_inv,
+                                   const float *thr_host, const uint32_t *code_thr, uint32_t cell_cap,
+                                   uint32_t group_cap, uint32_t cand_cap, int workgroups, hipStream_t st) {
+    const int levels = harm_levels(nharm_max);
+    if (levels < 0 || (log2s != 12 && log2s != 13) || ntrials <= 0 || ntrials > kBatchMaxTrials || slots <= 0 ||
+        workgroups <= 0 || nz > 65535)
+        return hipErrorInvalidValue;
+    BatchArgs a{};
+    a.trials = trials;
+    a.tiles = tiles;
+    a.ctl = ctl;
+    a.bank = bank;
+    a.ntrials = ntrials;
+    a.slots = slots;
+    a.nz = nz;
+    a.tpb = tpb;
+    a.h = h;
+    a.W = W;
+    a.izc = izc;
+    a.ntiles = ntiles;
+    a.cell_cap = cell_cap & ~1u;  // whole blocks, as launch_harmsum
+    a.group_cap = group_cap;
+    a.cand_cap = cand_cap;
+    a.code_inv = code_inv;
+    for (int l = 0; l <= levels; ++l) {
+        if (code_thr[l] > 0x8000u) return hipErrorInvalidValue;
+        a.thr.v[l] = thr_host[l];
+        a.T.k[l] = (0x8000u - code_thr[l]) * 0x10001u;
+    }
+#define CALL(LS, LV)                                                                                     \
+    if (log2s == LS && levels == LV)                                                                     \
+        hipLaunchKernelGGL((k_batch<LS, LV>), dim3(unsigned(workgroups)), dim3(256), 0, st, a);
+    CALL(12, 0) CALL(12, 1) CALL(12, 2) CALL(12, 3) CALL(12, 4)
+    CALL(13, 0) CALL(13, 1) CALL(13, 2) CALL(13, 3) CALL(13, 4)
 #undef CALL
     return hipGetLastError();
 }

@@ -146,4 +146,63 @@ hipError_t launch_refine(const float2 *X, const double *med, int W, int64_t nb, 
 hipError_t launch_interp_points(const float2 *X, const double *med, int W, int64_t nb, int h, const double *r,
                                 const double *z, const int32_t *nh, int64_t n, double *out, hipStream_t st);
 
+// ------------------------------------------------ persistent batch launch
+// Stages of one trial in the persistent batch kernel, in dependency order:
+// segment DFTs, correlation (segment x template block), harmonic-sum screen,
+// exact sums of the flagged cells, neighbour test of the hits.
+enum BatchStage { BST_SEG = 0, BST_CORR = 1, BST_SCREEN = 2, BST_EXACT = 3, BST_PEAK = 4, BST_N = 5 };
+
+// Per-trial descriptor (device memory).  X, med, seg, cnt and cands belong to
+// the trial; plane, codes and hits to the ring slot it runs in.
+struct BatchTrial {
+    const float2 *X;
+    const double *med;
+    float2 *seg;
+    float *plane;
+    uint8_t *codes;
+    void *hits;  // harmsum_scratch_bytes layout
+    uint32_t *cnt;  // six counters, zeroed before the launch
+    DevCand *cands;
+    int64_t nb;
+    int64_t nseg;
+    uint32_t ntile[BST_N];  // tiles of each stage
+    uint32_t pad;
+};
+
+// The global tile order: one packed word per tile, stage in bits 29-31,
+// trial in bits 23-28, tile index within the stage in bits 0-22.
+constexpr int kBatchMaxTrials = 64;
+constexpr uint32_t batch_tile(uint32_t stage, uint32_t trial, uint32_t idx) {
+    return (stage << 29) | (trial << 23) | idx;
+}
+constexpr uint32_t kBatchMaxStageTiles = 1u << 23;
+
+// Control words: [0] next tile, [1] error flag (1: a dependency wait ran
+// out, 2: a malformed tile word), [2..5] the first timed-out wait (stage,
+// trial, count seen, count awaited), [6..7] unused, then done[stage][trial]
+// (BST_N x ntrials tile counts).  Zeroed before the launch.
+constexpr int kBatchCtlHead = 8;
+
+// Tiles of the exact-sum and neighbour-test stages per trial.
+constexpr uint32_t kBatchExactTiles = 128;
+constexpr uint32_t kBatchPeakTiles = 128;
+// Screen tiles: (nb / 8192 rounded up) column tiles x (nz / 8 rounded up) row bands.
+uint32_t batch_screen_tiles(int64_t nb, int nz);
+
+// The persistent kernel: `workgroups` workgroups take tiles of the global
+// order from ctl[0] until it is exhausted.  A tile waits (bounded) until the
+// tiles it depends on are done: correlation on the trial's segment DFTs and,
+// from trial `slots` on, on the neighbour test of trial - slots (whose ring
+// slot it reuses); screen on the correlation; exact sums on the screen;
+// neighbour test on the exact sums.  Every dependency precedes its dependent
+// in the order, so the launch cannot deadlock.  log2s 12 or 13, no half-bin
+// plane.
+hipError_t launch_batch_persistent(int log2s, int nharm_max, const BatchTrial *trials, int ntrials,
+                                   const uint32_t *tiles, uint32_t ntiles, uint32_t *ctl, int slots,
+                                   const float2 *bank, int nz, int tpb, int h, int W, int izc, float code_inv,
+                                   const float *thr_host, const uint32_t *code_thr, uint32_t cell_cap,
+                                   uint32_t group_cap, uint32_t cand_cap, int workgroups, hipStream_t st);
+// Workgroups of the persistent kernel that fit the device at once.
+hipError_t batch_persistent_workgroups(int log2s, int nharm_max, int *per_cu);
+
 }  // namespace fdas

@@ -3,13 +3,17 @@
 // Requests (float32 host series of power-of-two lengths) are copied into
 // pinned host staging on fdas_submit and queued.  One scheduler thread owns
 // every HIP call: it admits queued requests in arrival order while a slot is
-// free and the request's device bytes fit the HBM budget (reusing a cached
-// work buffer of the same length, or allocating one, or evicting idle cached
+// free and the request's device bytes fit (the HBM budget given at creation,
+// or the device's free HBM read at admission time; reusing a cached work
+// buffer of the same length, or allocating one, or evicting idle cached
 // buffers of other lengths), enqueues the host-to-device copy and the whole
-// search on the slot's stream, and polls slots for completion.  Slots run
-// concurrently, so requests arriving while others are on the GPU join the
-// work already in flight.  The kernels take no decision that depends on what
-// else is running, so each result equals the same series searched alone.
+// search on the slot's stream, and polls slots for completion without
+// blocking: a finished search's records are copied asynchronously into a
+// page-locked result buffer (from a pool), and the request completes when
+// that copy has.  Slots run concurrently, so requests arriving while others
+// are on the GPU join the work already in flight.  The kernels take no
+// decision that depends on what else is running, so each result equals the
+// same series searched alone.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -35,11 +39,18 @@ struct Request {
     clk::time_point t_submit;
 };
 
+// Page-locked record buffer of a finished request (from the server's pool).
+struct Pinned {
+    fdas_cand *p = nullptr;
+    int64_t cap = 0;
+};
+
 struct Result {
     uint64_t tag = 0;
     fdas_status status = FDAS_OK;
     std::string error;
-    std::vector<fdas_cand> cands;
+    Pinned recs;     // the first n records
+    int64_t n = 0;
     int64_t found = 0;
     double latency = 0.0;
 };
@@ -52,10 +63,15 @@ struct Buffers {
 
 struct Slot {
     hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
+    hipEvent_t done = nullptr;    // search and count copy finished
+    hipEvent_t copied = nullptr;  // records copied into `out`
     bool busy = false;
+    bool copying = false;
     Request req;
     Buffers *buf = nullptr;
+    Pinned out;
+    int64_t n = 0, found = 0;
+    bool lost = false;
 };
 
 }  // namespace
@@ -63,8 +79,9 @@ struct Slot {
 struct fdas_server_s {
     fdas_plan_s *core = nullptr;  // options, thresholds, bank; no work buffers
     int64_t max_nsamp = 0;
-    int64_t budget = 0;
-    int64_t used = 0;  // device bytes held by work buffers
+    int64_t budget = 0;   // fixed budget; 0 = the device's free HBM at admission time
+    int64_t reserve = 0;  // free HBM left untouched in that mode
+    int64_t used = 0;     // device bytes held by work buffers
     std::vector<Slot> slots;
     std::multimap<int64_t, Buffers *> idle;  // cached buffers by length
 
@@ -73,6 +90,7 @@ struct fdas_server_s {
     std::deque<Request> pending;
     std::deque<Result> done;
     std::map<int64_t, std::vector<float *>> pinned;  // free staging by length
+    std::vector<Pinned> result_pool;                  // free page-locked record buffers
     int64_t outstanding = 0;
     bool stop = false;
     std::thread thread;
@@ -92,36 +110,118 @@ static void free_buffers(Buffers *b) {
     delete b;
 }
 
+// A free page-locked record buffer of at least n records (scheduler thread).
+static bool take_result_buffer(fdas_server_s *sv, int64_t n, Pinned *out) {
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        for (size_t i = 0; i < sv->result_pool.size(); ++i) {
+            if (sv->result_pool[i].cap >= n) {
+                *out = sv->result_pool[i];
+                sv->result_pool.erase(sv->result_pool.begin() + std::ptrdiff_t(i));
+                return true;
+            }
+        }
+    }
+    int64_t cap = 4096;
+    while (cap < n) cap *= 2;
+    Pinned b;
+    if (hipHostMalloc(reinterpret_cast<void **>(&b.p), size_t(cap) * sizeof(fdas_cand), hipHostMallocDefault) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    b.cap = cap;
+    *out = b;
+    return true;
+}
+
+// Whether `need` more device bytes may be allocated now.
+static bool fits(fdas_server_s *sv, int64_t need) {
+    if (sv->budget > 0) return sv->used + need <= sv->budget;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
+    return int64_t(fr) - sv->reserve >= need;
+}
+
 // Scheduler thread: admission, launch, completion.
 static void scheduler(fdas_server_s *sv) {
     (void)hipSetDevice(sv->core->device);
     for (;;) {
         bool progressed = false;
-        // ---- completions
+        // ---- completions: search done -> records copied -> result
         for (Slot &sl : sv->slots) {
             if (!sl.busy) continue;
-            const hipError_t q = hipEventQuery(sl.done);
-            if (q == hipErrorNotReady) continue;
             Result res;
             res.tag = sl.req.tag;
-            Workspace &ws = sl.buf->ws;
-            if (q != hipSuccess) {
-                res.status = FDAS_E_DEVICE;
-                res.error = std::string("request failed: ") + hipGetErrorString(q);
+            bool finished = false;
+            if (!sl.copying) {
+                const hipError_t q = hipEventQuery(sl.done);
+                if (q == hipErrorNotReady) continue;
+                Workspace &ws = sl.buf->ws;
+                if (q != hipSuccess) {
+                    res.status = FDAS_E_DEVICE;
+                    res.error = std::string("request failed: ") + hipGetErrorString(q);
+                    finished = true;
+                } else {
+                    sl.found = ws.h_count[0];
+                    sl.lost = ws.h_count[2] != 0;
+                    sl.n = std::min<int64_t>(sl.found, sv->core->cand_cap);
+                    hipError_t e = hipSuccess;
+                    if (sl.n > 0) {
+                        if (!take_result_buffer(sv, sl.n, &sl.out)) {
+                            res.status = FDAS_E_NOMEM;
+                            res.error = "page-locked result buffer allocation failed";
+                            finished = true;
+                        } else {
+                            e = hipMemcpyAsync(sl.out.p, ws.final, size_t(sl.n) * sizeof(fdas_cand),
+                                               hipMemcpyDeviceToHost, sl.stream);
+                        }
+                    }
+                    if (!finished) {
+                        if (e == hipSuccess) e = hipEventRecord(sl.copied, sl.stream);
+                        if (e != hipSuccess) {
+                            res.status = FDAS_E_DEVICE;
+                            res.error = std::string("copy candidates: ") + hipGetErrorString(e);
+                            finished = true;
+                        } else {
+                            sl.copying = true;
+                            progressed = true;
+                            continue;
+                        }
+                    }
+                }
             } else {
-                const int64_t n = std::min<int64_t>(*ws.h_count, sv->core->cand_cap);
-                res.cands.resize(size_t(n));
-                int64_t found = 0;
-                res.status = copy_candidates(sv->core, ws, res.cands.data(), n, &found, sl.stream);
-                res.found = found;
-                if (res.status != FDAS_OK) res.error = g_last_error;
+                const hipError_t q = hipEventQuery(sl.copied);
+                if (q == hipErrorNotReady) continue;
+                if (q != hipSuccess) {
+                    res.status = FDAS_E_DEVICE;
+                    res.error = std::string("copy candidates: ") + hipGetErrorString(q);
+                } else {
+                    res.recs = sl.out;
+                    sl.out = Pinned{};
+                    res.n = sl.n;
+                    res.found = sl.found;
+                    if (sl.lost) {
+                        res.status = FDAS_E_OVERFLOW;
+                        res.error = "harmonic-sum cell list capacity exceeded: candidates incomplete "
+                                    "(raise cand_capacity)";
+                    } else if (sl.found > int64_t(sv->core->cand_cap)) {
+                        res.status = FDAS_E_OVERFLOW;
+                        res.error = "candidate capacity exceeded";
+                    }
+                }
+                finished = true;
             }
+            if (!finished) continue;
             res.latency = std::chrono::duration<double>(clk::now() - sl.req.t_submit).count();
             std::lock_guard<std::mutex> lk(sv->mu);
+            if (sl.out.p) sv->result_pool.push_back(sl.out);  // an error left it unused
+            sl.out = Pinned{};
             sv->pinned[sl.req.nsamp].push_back(sl.req.host);
             sv->idle.emplace(sl.req.nsamp, sl.buf);
             sl.buf = nullptr;
             sl.busy = false;
+            sl.copying = false;
             sv->done.push_back(std::move(res));
             sv->cv_done.notify_all();
             progressed = true;
@@ -153,7 +253,7 @@ static void scheduler(fdas_server_s *sv) {
                 const int64_t need = buffer_bytes(sv->core, req.nsamp);
                 // evict idle buffers of other lengths until the request fits
                 for (;;) {
-                    if (sv->used + need <= sv->budget) break;
+                    if (fits(sv, need)) break;
                     Buffers *victim = nullptr;
                     {
                         std::lock_guard<std::mutex> lk(sv->mu);
@@ -165,7 +265,7 @@ static void scheduler(fdas_server_s *sv) {
                     sv->used -= victim->bytes;
                     free_buffers(victim);
                 }
-                if (sv->used + need > sv->budget) break;  // wait for a running request to finish
+                if (!fits(sv, need)) break;  // wait for a running request to finish
                 buf = new Buffers;
                 buf->bytes = need;
                 fdas_status s = alloc_workspace(sv->core, buf->ws, req.nsamp);
@@ -262,26 +362,30 @@ fdas_status fdas_server_create(const fdas_bank *bank, int32_t seg, const fdas_op
     auto *sv = new fdas_server_s;
     sv->core = core;
     sv->max_nsamp = max_nsamp;
-    if (hbm_budget == 0) {
-        size_t fr = 0, tot = 0;
-        if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = 0;
-        hbm_budget = size_t(double(fr) * 0.9);
-    }
     sv->budget = int64_t(hbm_budget);
-    if (sv->budget < buffer_bytes(core, max_nsamp)) {
-        fdas_plan_destroy(core);
-        delete sv;
-        set_error("HBM budget smaller than one request of max_nsamp");
-        return FDAS_E_NOMEM;
+    {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) fr = tot = 0;
+        sv->reserve = (int64_t(512) << 20) + int64_t(tot / 100);
+        const int64_t room = hbm_budget ? sv->budget : int64_t(fr) - sv->reserve;
+        if (room < buffer_bytes(core, max_nsamp)) {
+            fdas_plan_destroy(core);
+            delete sv;
+            set_error(hbm_budget ? "HBM budget smaller than one request of max_nsamp"
+                                 : "free HBM smaller than one request of max_nsamp");
+            return FDAS_E_NOMEM;
+        }
     }
     sv->slots.resize(size_t(max_slots));
     for (Slot &sl : sv->slots) {
         hipError_t e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.copied, hipEventDisableTiming);
         if (e != hipSuccess) {
             for (Slot &x : sv->slots) {
                 if (x.stream) (void)hipStreamDestroy(x.stream);
                 if (x.done) (void)hipEventDestroy(x.done);
+                if (x.copied) (void)hipEventDestroy(x.copied);
             }
             fdas_plan_destroy(core);
             delete sv;
@@ -360,8 +464,12 @@ fdas_status fdas_poll(fdas_server *sv, uint64_t *tag, fdas_cand *cands, int64_t 
     lk.unlock();
     if (tag) *tag = res.tag;
     if (latency_s) *latency_s = res.latency;
-    const int64_t n = std::min<int64_t>(int64_t(res.cands.size()), cap);
-    for (int64_t i = 0; i < n; ++i) cands[i] = res.cands[size_t(i)];
+    const int64_t n = std::min<int64_t>(res.n, cap);
+    if (n > 0) std::memcpy(cands, res.recs.p, size_t(n) * sizeof(fdas_cand));
+    if (res.recs.p) {
+        std::lock_guard<std::mutex> lk2(sv->mu);
+        sv->result_pool.push_back(res.recs);
+    }
     if (ncands) *ncands = res.status == FDAS_OK || res.status == FDAS_E_OVERFLOW ? res.found : 0;
     if (res.status != FDAS_OK) {
         set_error(res.error);
@@ -392,9 +500,14 @@ void fdas_server_destroy(fdas_server *sv) {
     if (sv->thread.joinable()) sv->thread.join();
     for (Slot &sl : sv->slots) {
         if (sl.buf) free_buffers(sl.buf);
+        if (sl.out.p) (void)hipHostFree(sl.out.p);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.copied) (void)hipEventDestroy(sl.copied);
     }
+    for (Pinned &b : sv->result_pool) (void)hipHostFree(b.p);
+    for (Result &r : sv->done)
+        if (r.recs.p) (void)hipHostFree(r.recs.p);
     for (auto &kv : sv->idle) free_buffers(kv.second);
     for (auto &kv : sv->pinned)
         for (float *p : kv.second) (void)hipHostFree(p);
