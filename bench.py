@@ -168,13 +168,30 @@ def bench_batched(fdas, bank, xs, per_call: int, host=None):
     copied from page-locked host memory (PCIe included): calls of per_call / 2
     trials, each call's copies overlapping the previous call's search on a
     second stream."""
+    import numpy as np
     import torch
     seg_b, tpb_b, tune_ms = fdas.autotune(bank, N, nharm_max=NHARM, sigma=SIGMA)
     log(f"batched: {len(xs)} trials, {per_call} per call, segment {seg_b}, {tpb_b} templates per block")
-    planb = fdas.Plan(bank, N, seg_b, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb_b)
     bcap = 1 << 19
     bout = fdas.pinned_candidates(bcap * per_call)
-    counts = [len(c) for c in planb.search_batch(xs[:per_call], caps=[bcap] * per_call, out=bout)]  # allocates
+    # the other launch form first: per-trial graphs on two streams
+    plans = fdas.Plan(bank, N, seg_b, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb_b,
+                      batch_launch="streams")
+    ref = [c.copy() for c in plans.search_batch(xs[:per_call], caps=[bcap] * per_call, out=bout)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(0, len(xs), per_call):
+        chunk = xs[i:i + per_call]
+        plans.search_batch(chunk, caps=[bcap] * len(chunk), out=bout)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    plans.close()
+    streams = {"value": round(len(xs) / ts, 3), "unit": "DM trials/s", "ms_per_trial": round(1e3 * ts / len(xs), 4),
+               "launch": "per-trial graphs on two streams (fdas_opts.batch_launch = FDAS_BATCH_STREAMS)"}
+    planb = fdas.Plan(bank, N, seg_b, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb_b)
+    got = planb.search_batch(xs[:per_call], caps=[bcap] * per_call, out=bout)  # allocates
+    counts = [len(c) for c in got]
+    streams["same_records_as_persistent"] = all(np.array_equal(a, b) for a, b in zip(got, ref))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(0, len(xs), per_call):
@@ -229,6 +246,7 @@ def bench_batched(fdas, bank, xs, per_call: int, host=None):
             "trials_per_call": per_call, "ms_per_trial": round(1e3 * tb / len(xs), 4),
             "launch": "one persistent-kernel launch per call of up to 64 trials" if seg_b in (4096, 8192)
                       else "per-trial graphs on two streams",
+            "per_trial_graphs": streams,
             "candidates_per_trial": {"min": min(counts), "max": max(counts), "mean": round(sum(counts) / len(counts), 1)},
             "data": "64 distinct trials, seeds 1000-1063, 0-3 pulsars each, resident in HBM",
             "autotuned": {"segment": seg_b, "templates_per_block": tpb_b,

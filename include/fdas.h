@@ -86,7 +86,10 @@ typedef struct fdas_opts {
     int32_t correlator;          /* FDAS_CORR_FFT_F32 (default) or a matrix form, see below   */
     int32_t refine_levels;       /* candidate refinement levels, 0 = off (default), <= 20     */
     int32_t interbin;            /* 1 = half-bin plane (2 Nb columns), 0 = off (default)      */
+    int32_t batch_launch;        /* fdas_search_batch: FDAS_BATCH_PERSISTENT (default) or     */
+                                 /* FDAS_BATCH_STREAMS, see fdas_search_batch                 */
 } fdas_opts;
+enum { FDAS_BATCH_PERSISTENT = 0, FDAS_BATCH_STREAMS = 1 };
 
 /* Half-bin plane (interbin = 1), an extension past the paper's method: a
  * second template bank at offsets q + 1/2, T'_z[q] = conj(A(q + 1/2, z)) /
@@ -266,7 +269,8 @@ fdas_status fdas_plan_search_counts(const fdas_plan_t *plan, int64_t *out3);
  * nsamp[i] <= the plan's nsamp, through the hot path (no plane is returned).
  * The work is ordered after what hip_stream holds when the call is made, and
  * hip_stream is ordered after it on return.
- * With the FFT correlator, segment length 4096 or 8192 and no half-bin plane,
+ * With opts.batch_launch FDAS_BATCH_PERSISTENT (the default), the FFT
+ * correlator, segment length 4096 or 8192 and no half-bin plane,
  * up to 64 trials at a time go through ONE launch of a persistent kernel (a
  * longer batch takes one launch per 64): per trial the real DFT and block
  * medians run first, then the persistent workgroups take tiles from a device
@@ -280,10 +284,13 @@ fdas_status fdas_plan_search_counts(const fdas_plan_t *plan, int64_t *out3);
  * the first such call and kept by the plan: per trial (up to 64) its
  * spectrum, medians, segment spectra and candidate records; four plane /
  * screening-code / list slots shared round-robin by the trials.
- * Other plans: consecutive trials alternate between two library-owned
- * streams and two work buffers, so that one trial's harmonic sums overlap the
- * next trial's correlation, each trial's launches captured once per length
- * in a HIP graph.
+ * With FDAS_BATCH_STREAMS, and for other plans: consecutive trials alternate
+ * between two library-owned streams and two work buffers, so that one
+ * trial's harmonic sums overlap the next trial's correlation, each trial's
+ * launches captured once per length in a HIP graph (the standalone kernels
+ * at their own occupancy: faster on MI355X, where the persistent kernel runs
+ * its memory-bound harmonic-sum tiles at the correlation's 2 workgroups per
+ * compute unit).
  * Either way a batch leaves the buffers of fdas_search alone: the
  * inspection, interpolation, refinement and work-count calls keep describing
  * the plan's last fdas_search.  Trial i's candidates go to

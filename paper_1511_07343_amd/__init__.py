@@ -42,7 +42,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("nharm_max", ctypes.c_int32),
                 ("median_window", ctypes.c_int32), ("cand_capacity", ctypes.c_int64),
                 ("templates_per_block", ctypes.c_int32), ("correlator", ctypes.c_int32),
-                ("refine_levels", ctypes.c_int32), ("interbin", ctypes.c_int32)]
+                ("refine_levels", ctypes.c_int32), ("interbin", ctypes.c_int32),
+                ("batch_launch", ctypes.c_int32)]
 
 
 CAND_DTYPE = np.dtype([("k", "<i8"), ("iz", "<i4"), ("nharm", "<i4"), ("r", "<f8"), ("z", "<f8"),
@@ -141,10 +142,12 @@ def _stream_handle(stream=None):
 # Correlators (fdas_opts.correlator): FP32 overlap-save FFTs, or Eq. (1) as a
 # matrix product with BF16 / FP16 operands and FP32 accumulation.
 CORRELATORS = {"fft": 0, "bf16": 1, "f16": 2}
+# fdas_search_batch launch forms (fdas_opts.batch_launch)
+BATCH_LAUNCH = {"persistent": 0, "streams": 1}
 
 
 def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=0, templates_per_block=0, correlator="fft",
-          refine_levels=0, interbin=False):
+          refine_levels=0, interbin=False, batch_launch="persistent"):
     o = _Opts()
     load().fdas_default_opts(ctypes.byref(o))
     o.sigma = float(sigma)
@@ -157,6 +160,9 @@ def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=0, template
     o.correlator = CORRELATORS[correlator]
     o.refine_levels = int(refine_levels)
     o.interbin = int(bool(interbin))
+    if batch_launch not in BATCH_LAUNCH:
+        raise ValueError(f"batch_launch must be one of {sorted(BATCH_LAUNCH)}")
+    o.batch_launch = BATCH_LAUNCH[batch_launch]
     return o
 
 

@@ -95,7 +95,7 @@ void destroy_pbatch(PBatch *pb) {
 
 // Whether the persistent launch serves this plan.
 static bool persistent_ok(const fdas_plan_s *p) {
-    return !p->td && p->corr == FDAS_CORR_FFT_F32 && !p->opts.interbin && (p->log2s == 12 || p->log2s == 13) &&
+    return p->opts.batch_launch == FDAS_BATCH_PERSISTENT && !p->td && p->corr == FDAS_CORR_FFT_F32 && !p->opts.interbin && (p->log2s == 12 || p->log2s == 13) &&
            p->nz <= 65535 && p->nsamp / 2 >= 32;
 }
 

@@ -71,6 +71,10 @@ fdas_status validate_opts(const fdas_opts &o) {
         set_error("the half-bin plane needs the FFT correlator");
         return FDAS_E_INVAL;
     }
+    if (o.batch_launch != FDAS_BATCH_PERSISTENT && o.batch_launch != FDAS_BATCH_STREAMS) {
+        set_error("opts.batch_launch must be FDAS_BATCH_PERSISTENT or FDAS_BATCH_STREAMS");
+        return FDAS_E_INVAL;
+    }
     return FDAS_OK;
 }
 

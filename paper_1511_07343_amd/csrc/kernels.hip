@@ -442,10 +442,25 @@ __device__ __forceinline__ void correlate_item(float2 *lds, const Twiddles<FftSh
         int to = t;
         asm volatile("" : "+v"(to));
         const __amdgpu_buffer_rsrc_t rbz = buffer_rsrc((second ? bank_half : bank) + int64_t(iz) * Sh::S, Sh::S * 8);
+        // The operand loads go out in two batches of R / 2 points, each
+        // batch issued before any of its products is formed (the scheduling
+        // barriers keep the compiler from interleaving loads and multiplies,
+        // which under register pressure it does by waiting for each pair in
+        // turn: one memory round trip per point).
         float2 v[Sh::R];
+        static_for<0, 2>([&](auto hc) {
+            constexpr int m0 = decltype(hc)::value * (Sh::R / 2);
+            float2 b[Sh::R / 2];
 #pragma unroll
-        for (int m = 0; m < Sh::R; ++m)
-            v[m] = cmul(buffer_load_f2(rsp, to, Sh::NT * m), buffer_load_f2(rbz, to, Sh::NT * m));
+            for (int m = 0; m < Sh::R / 2; ++m) {
+                v[m0 + m] = buffer_load_f2(rsp, to, Sh::NT * (m0 + m));
+                b[m] = buffer_load_f2(rbz, to, Sh::NT * (m0 + m));
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int m = 0; m < Sh::R / 2; ++m) v[m0 + m] = cmul(v[m0 + m], b[m]);
+            __builtin_amdgcn_sched_barrier(0);
+        });
         fft_wg<Sh, +1>(v, lds, tw, t);
         // Powers through LDS so that each thread stores 4 consecutive
         // points: point n sits at LDS index n + sh, which puts chunk c

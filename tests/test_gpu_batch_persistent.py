@@ -104,3 +104,23 @@ def test_persistent_batch_overflow_reports_counts(gpu_lib):
     assert e.value.status == -4
     plan.close()
     bank.close()
+
+
+def test_stream_launch_equals_persistent(gpu_lib):
+    # the other launch form of fdas_search_batch (per-trial graphs on two
+    # streams) on the same trials gives the same records
+    lens = [1 << 17, 1 << 16, 1 << 17, 1 << 15, 1 << 17, 1 << 16]
+    trials = _trials(lens, 800)
+    bank = gpu_lib.make_templates(ZMAX, DZ)
+    xs = [_dev(t.x) for t in trials]
+    a = gpu_lib.Plan(bank, 1 << 17, 4096, **OPTS)
+    b = gpu_lib.Plan(bank, 1 << 17, 4096, batch_launch="streams", **OPTS)
+    got_a = a.search_batch(xs, caps=[100000] * len(xs))
+    got_b = b.search_batch(xs, caps=[100000] * len(xs))
+    for i, (x, y) in enumerate(zip(got_a, got_b)):
+        assert np.array_equal(x, y), i
+    with pytest.raises(ValueError):
+        gpu_lib.Plan(bank, 1 << 17, 4096, batch_launch="both", **OPTS)
+    a.close()
+    b.close()
+    bank.close()
