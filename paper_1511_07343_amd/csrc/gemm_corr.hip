@@ -12,6 +12,7 @@
 // its screening code go to the same plane layout the FFT path writes.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <vector>
@@ -58,7 +59,7 @@ __host__ __device__ inline uint16_t to_half_bits(float x) {
 constexpr int GM_WAVES = 4;
 constexpr int GM_RT = 8;                         // row tiles of 16 bins per wave
 constexpr int GM_ROWS = GM_WAVES * GM_RT * 16;   // bins per row block
-constexpr int GM_TZ = 32;                        // templates per slice
+constexpr int GM_TZ = 16;                        // templates per slice
 constexpr int GM_CT = 2 * GM_TZ / 16;            // column tiles: Re, then Im, of the slice's templates
 constexpr int GM_WIN = 16;                       // A fragments kept per wave (power of two >= GM_RT + 1)
 constexpr int GM_FRAG = 64;                      // 16-byte fragments per MFMA operand (one per lane)
@@ -89,6 +90,9 @@ __global__ __launch_bounds__(256) void k_lowp_spectrum(const float2 *__restrict_
 
 // One workgroup: the B fragments of one template slice (all K) staged in LDS,
 // then row blocks of GM_ROWS bins, each through a spectrum window in LDS.
+// The LDS holds gemm_lds_bytes(nk): slices of 16 templates keep it small
+// enough for two workgroups per CU up to about 30 K steps, so that the MFMA
+// units of a SIMD have two waves to switch between.
 // Wave w owns rows [128 w, 128 w + 128) of a block (8 row tiles) and all
 // GM_CT column tiles (Re of the slice's templates, 16 per tile, then Im).
 //
@@ -103,13 +107,14 @@ __global__ __launch_bounds__(256) void k_lowp_spectrum(const float2 *__restrict_
 // powers are stored, so that the stores drain while the next block runs
 // (vector-memory counters count loads and stores together).
 template <bool BF16>
-__global__ __launch_bounds__(64 * GM_WAVES, 1) void k_corr_gemm(
+__global__ __launch_bounds__(64 * GM_WAVES, 2) void k_corr_gemm(
     const uint32_t *__restrict__ xl, int64_t nb, int h, int nk, const uint4 *__restrict__ bfrag, int nz, int nsl,
     int64_t nrb, int64_t per, float power_scale, float *__restrict__ plane, uint8_t *__restrict__ codes,
     float code_inv) {
-    __shared__ uint4 bl[GM_MAX_KSTEPS * GM_SLICE_FRAGS];
-    __shared__ uint4 win4[GM_WORDS(GM_MAX_KSTEPS)];  // 4 copies x GM_WORDS(nk) / 4 uint4
-    uint32_t *__restrict__ win = reinterpret_cast<uint32_t *>(win4);
+    extern __shared__ uint4 gm_lds[];
+    uint4 *__restrict__ bl = gm_lds;  // nk GM_SLICE_FRAGS fragments
+    // then 4 copies x GM_WORDS(nk) words
+    uint32_t *__restrict__ win = reinterpret_cast<uint32_t *>(gm_lds + nk * GM_SLICE_FRAGS);
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int i16 = lane & 15, kg = lane >> 4;
     const int uw = GM_WORDS(nk);
@@ -227,6 +232,8 @@ __global__ __launch_bounds__(64 * GM_WAVES, 1) void k_corr_gemm(
 
 int gemm_ksteps(int h) { return (2 * (2 * h + 1) + 31) / 32; }
 
+static size_t gemm_lds_bytes(int nk) { return size_t(nk * GM_SLICE_FRAGS + GM_WORDS(nk)) * 16; }
+
 size_t gemm_bank_bytes(int nz, int h) {
     return size_t((nz + GM_TZ - 1) / GM_TZ) * size_t(gemm_ksteps(h)) * GM_SLICE_FRAGS * 16;
 }
@@ -270,15 +277,22 @@ hipError_t launch_corr_gemm(const uint32_t *xl, int64_t nb, int h, const void *b
     if (nk > GM_MAX_KSTEPS || nb % 4 != 0 || workgroups <= 0) return hipErrorInvalidValue;
     const int nsl = (nz + GM_TZ - 1) / GM_TZ;
     const int64_t nrb = (nb + GM_ROWS - 1) / GM_ROWS;
+    const size_t lds = gemm_lds_bytes(nk);
+    // workgroups per CU that fit beside each other (the LDS decides)
+    int per_cu = 0;
+    hipError_t e = bf16 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_corr_gemm<true>, 64 * GM_WAVES, lds)
+                        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_corr_gemm<false>, 64 * GM_WAVES, lds);
+    if (e != hipSuccess) return e;
+    workgroups *= std::max(per_cu, 1);
     const int64_t per = (int64_t(nsl) * nrb + workgroups - 1) / workgroups;
     const int64_t grid = (int64_t(nsl) * nrb + per - 1) / per;
     const float scale = float(1.0 / (GM_TAP_SCALE * GM_TAP_SCALE));
     const uint4 *bf = static_cast<const uint4 *>(bank);
     if (bf16)
-        hipLaunchKernelGGL(k_corr_gemm<true>, dim3(unsigned(grid)), dim3(64 * GM_WAVES), 0, st, xl, nb, h, nk, bf, nz,
+        hipLaunchKernelGGL(k_corr_gemm<true>, dim3(unsigned(grid)), dim3(64 * GM_WAVES), lds, st, xl, nb, h, nk, bf, nz,
                            nsl, nrb, per, scale, plane, codes, code_inv);
     else
-        hipLaunchKernelGGL(k_corr_gemm<false>, dim3(unsigned(grid)), dim3(64 * GM_WAVES), 0, st, xl, nb, h, nk, bf,
+        hipLaunchKernelGGL(k_corr_gemm<false>, dim3(unsigned(grid)), dim3(64 * GM_WAVES), lds, st, xl, nb, h, nk, bf,
                            nz, nsl, nrb, per, scale, plane, codes, code_inv);
     return hipGetLastError();
 }

@@ -1111,6 +1111,22 @@ __device__ __forceinline__ bool batch_wait(uint32_t *done, uint32_t target, uint
     }
 }
 
+// The trial descriptor in scalar registers.  Its fields come from memory
+// that the kernel also writes, so the compiler cannot prove them uniform: it
+// would keep them in vector registers and turn every buffer access through a
+// resource built from them into a loop over the lanes' distinct values.
+__device__ __forceinline__ BatchTrial uniform_trial(const BatchTrial *p) {
+    constexpr int NW = sizeof(BatchTrial) / 4;
+    static_assert(sizeof(BatchTrial) % 4 == 0, "whole words");
+    uint32_t w[NW];
+    __builtin_memcpy(w, p, sizeof(BatchTrial));
+#pragma unroll
+    for (int i = 0; i < NW; ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    BatchTrial r;
+    __builtin_memcpy(&r, w, sizeof(BatchTrial));
+    return r;
+}
+
 // Workgroups take tiles of the global order from ctl[0]; see
 // launch_batch_persistent.  Correlation tiles of a trial walk its segments
 // template block by template block, so that every XCD keeps one block's
@@ -1186,7 +1202,7 @@ __global__ __launch_bounds__(256, 2) void k_batch(BatchArgs a) {
         const uint32_t trial = __builtin_amdgcn_readfirstlane(tinfo[1]);
         const uint32_t idx = __builtin_amdgcn_readfirstlane(tinfo[2]);
         if (stage >= BST_N) break;
-        const BatchTrial &tr = a.trials[trial];
+        const BatchTrial tr = uniform_trial(a.trials + trial);
         // The thread index made opaque per tile, so that the twiddles of the
         // transform tiles are computed per tile instead of being hoisted out
         // of the loop (both directions' tables held across every tile would
