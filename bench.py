@@ -162,21 +162,22 @@ C4_LENGTHS = (1 << 21, 1 << 22, 1 << 23)
 
 
 def bench_batched(fdas, bank, xs, per_call: int, host=None):
-    """64 distinct trials through fdas_search_batch, per_call trials per call
-    (64: one launch of the persistent kernel), the series resident in HBM;
-    with `host` (the same series in host memory) also with the series first
-    copied from page-locked host memory (PCIe included): calls of per_call / 2
-    trials, each call's copies overlapping the previous call's search on a
-    second stream."""
+    """64 distinct trials through fdas_search_batch, per_call trials per call,
+    the series resident in HBM, in both launch forms: the default (per-trial
+    graphs on two streams) and the persistent kernel (one launch per call of
+    up to 64 trials); with `host` (the same series in host memory) also the
+    default form with the series first copied from page-locked host memory
+    (PCIe included): calls of per_call / 2 trials, each call's copies
+    overlapping the previous call's search on a second stream."""
     import numpy as np
     import torch
     seg_b, tpb_b, tune_ms = fdas.autotune(bank, N, nharm_max=NHARM, sigma=SIGMA)
     log(f"batched: {len(xs)} trials, {per_call} per call, segment {seg_b}, {tpb_b} templates per block")
     bcap = 1 << 19
     bout = fdas.pinned_candidates(bcap * per_call)
-    # the other launch form first: per-trial graphs on two streams
+    # the persistent kernel first
     plans = fdas.Plan(bank, N, seg_b, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb_b,
-                      batch_launch="streams")
+                      batch_launch="persistent")
     ref = [c.copy() for c in plans.search_batch(xs[:per_call], caps=[bcap] * per_call, out=bout)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -186,12 +187,14 @@ def bench_batched(fdas, bank, xs, per_call: int, host=None):
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
     plans.close()
-    streams = {"value": round(len(xs) / ts, 3), "unit": "DM trials/s", "ms_per_trial": round(1e3 * ts / len(xs), 4),
-               "launch": "per-trial graphs on two streams (fdas_opts.batch_launch = FDAS_BATCH_STREAMS)"}
+    persistent = {"value": round(len(xs) / ts, 3), "unit": "DM trials/s", "ms_per_trial": round(1e3 * ts / len(xs), 4),
+                  "launch": ("one persistent-kernel launch per call of up to 64 trials "
+                             "(fdas_opts.batch_launch = FDAS_BATCH_PERSISTENT)") if seg_b in (4096, 8192)
+                            else "per-trial graphs on two streams (no persistent form at this segment length)"}
     planb = fdas.Plan(bank, N, seg_b, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb_b)
     got = planb.search_batch(xs[:per_call], caps=[bcap] * per_call, out=bout)  # allocates
     counts = [len(c) for c in got]
-    streams["same_records_as_persistent"] = all(np.array_equal(a, b) for a, b in zip(got, ref))
+    persistent["same_records_as_default"] = all(np.array_equal(a, b) for a, b in zip(got, ref))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(0, len(xs), per_call):
@@ -244,9 +247,8 @@ def bench_batched(fdas, bank, xs, per_call: int, host=None):
     return {"value": round(len(xs) / tb, 3), "unit": "DM trials/s", "trials": len(xs),
             "h2d_included": h2d,
             "trials_per_call": per_call, "ms_per_trial": round(1e3 * tb / len(xs), 4),
-            "launch": "one persistent-kernel launch per call of up to 64 trials" if seg_b in (4096, 8192)
-                      else "per-trial graphs on two streams",
-            "per_trial_graphs": streams,
+            "launch": "per-trial graphs on two streams (fdas_opts.batch_launch = FDAS_BATCH_STREAMS, the default)",
+            "persistent": persistent,
             "candidates_per_trial": {"min": min(counts), "max": max(counts), "mean": round(sum(counts) / len(counts), 1)},
             "data": "64 distinct trials, seeds 1000-1063, 0-3 pulsars each, resident in HBM",
             "autotuned": {"segment": seg_b, "templates_per_block": tpb_b,

@@ -86,10 +86,10 @@ typedef struct fdas_opts {
     int32_t correlator;          /* FDAS_CORR_FFT_F32 (default) or a matrix form, see below   */
     int32_t refine_levels;       /* candidate refinement levels, 0 = off (default), <= 20     */
     int32_t interbin;            /* 1 = half-bin plane (2 Nb columns), 0 = off (default)      */
-    int32_t batch_launch;        /* fdas_search_batch: FDAS_BATCH_PERSISTENT (default) or     */
-                                 /* FDAS_BATCH_STREAMS, see fdas_search_batch                 */
+    int32_t batch_launch;        /* fdas_search_batch: FDAS_BATCH_STREAMS (default) or        */
+                                 /* FDAS_BATCH_PERSISTENT, see fdas_search_batch              */
 } fdas_opts;
-enum { FDAS_BATCH_PERSISTENT = 0, FDAS_BATCH_STREAMS = 1 };
+enum { FDAS_BATCH_STREAMS = 0, FDAS_BATCH_PERSISTENT = 1 };
 
 /* Half-bin plane (interbin = 1), an extension past the paper's method: a
  * second template bank at offsets q + 1/2, T'_z[q] = conj(A(q + 1/2, z)) /
@@ -269,8 +269,13 @@ fdas_status fdas_plan_search_counts(const fdas_plan_t *plan, int64_t *out3);
  * nsamp[i] <= the plan's nsamp, through the hot path (no plane is returned).
  * The work is ordered after what hip_stream holds when the call is made, and
  * hip_stream is ordered after it on return.
- * With opts.batch_launch FDAS_BATCH_PERSISTENT (the default), the FFT
- * correlator, segment length 4096 or 8192 and no half-bin plane,
+ * With opts.batch_launch FDAS_BATCH_STREAMS (the default), and for plans the
+ * persistent form does not cover: consecutive trials alternate between two
+ * library-owned streams and two work buffers, so that one trial's harmonic
+ * sums overlap the next trial's correlation, each trial's launches captured
+ * once per length in a HIP graph; every kernel runs at its own occupancy.
+ * With FDAS_BATCH_PERSISTENT, the FFT correlator, segment length 4096 or
+ * 8192 and no half-bin plane,
  * up to 64 trials at a time go through ONE launch of a persistent kernel (a
  * longer batch takes one launch per 64): per trial the real DFT and block
  * medians run first, then the persistent workgroups take tiles from a device
@@ -283,14 +288,11 @@ fdas_status fdas_plan_search_counts(const fdas_plan_t *plan, int64_t *out3);
  * candidates are sorted per trial afterwards.  Device memory, allocated on
  * the first such call and kept by the plan: per trial (up to 64) its
  * spectrum, medians, segment spectra and candidate records; four plane /
- * screening-code / list slots shared round-robin by the trials.
- * With FDAS_BATCH_STREAMS, and for other plans: consecutive trials alternate
- * between two library-owned streams and two work buffers, so that one
- * trial's harmonic sums overlap the next trial's correlation, each trial's
- * launches captured once per length in a HIP graph (the standalone kernels
- * at their own occupancy: faster on MI355X, where the persistent kernel runs
- * its memory-bound harmonic-sum tiles at the correlation's 2 workgroups per
- * compute unit).
+ * screening-code / list slots shared round-robin by the trials.  On MI355X
+ * the persistent form is the slower one (about 0.6 x the two-stream rate at
+ * 2^23 samples): its memory-bound harmonic-sum tiles run at the correlation
+ * tiles' occupancy of two workgroups per compute unit, which the separate
+ * kernels of the two-stream form do not share.
  * Either way a batch leaves the buffers of fdas_search alone: the
  * inspection, interpolation, refinement and work-count calls keep describing
  * the plan's last fdas_search.  Trial i's candidates go to

@@ -143,11 +143,11 @@ def _stream_handle(stream=None):
 # matrix product with BF16 / FP16 operands and FP32 accumulation.
 CORRELATORS = {"fft": 0, "bf16": 1, "f16": 2}
 # fdas_search_batch launch forms (fdas_opts.batch_launch)
-BATCH_LAUNCH = {"persistent": 0, "streams": 1}
+BATCH_LAUNCH = {"streams": 0, "persistent": 1}
 
 
 def _opts(sigma=6.0, nharm_max=16, median_window=1024, cand_capacity=0, templates_per_block=0, correlator="fft",
-          refine_levels=0, interbin=False, batch_launch="persistent"):
+          refine_levels=0, interbin=False, batch_launch="streams"):
     o = _Opts()
     load().fdas_default_opts(ctypes.byref(o))
     o.sigma = float(sigma)

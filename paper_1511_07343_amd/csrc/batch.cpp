@@ -1,25 +1,31 @@
-// fdas_search_batch: many series through the hot path.
+// fdas_search_batch: many series through the hot path, in one of two forms.
 //
-// Persistent path (segment lengths 4096 and 8192 of the FFT correlator, no
-// half-bin plane): up to 64 trials of mixed lengths go through ONE launch of
-// a persistent kernel.  Per trial, the real DFT and block medians run first
-// (small launches); then the persistent workgroups take tiles from a device
-// work queue (the global tile order built here): segment DFTs, correlation
-// tiles (segment x template block), harmonic-sum screen tiles, exact-sum and
-// neighbour-test tiles.  A per-trial, per-stage completion counter releases
-// the next stage's tiles of that trial, and the stages of consecutive trials
-// are interleaved, so one trial's memory-bound harmonic sums run beside the
-// next trial's ALU-bound correlation.  Planes, codes and harmonic-sum lists
-// live in a ring of kBatchSlots slots: trial t's correlation waits until
-// trial t - kBatchSlots has finished its neighbour test.  The upload of the
-// order, the clears, the per-trial front end, the persistent launch and the
-// copy-back of the counts are captured in one HIP graph per call; candidate
-// sorting and the copies to the host follow per trial.
-//
-// Other plans: consecutive trials on two streams and two work buffers, each
+// Two streams (the default, and every plan the persistent form does not
+// cover): consecutive trials on two streams and two work buffers, each
 // slot's per-trial launch sequence captured once per series length in a HIP
 // graph that reads the workspace's own input buffer (a trial is a
-// device-to-device copy into that buffer followed by a graph launch).
+// device-to-device copy into that buffer followed by a graph launch).  One
+// trial's memory-bound harmonic sums overlap the next trial's ALU-bound
+// correlation, each kernel at its own occupancy.
+//
+// Persistent (opts.batch_launch = FDAS_BATCH_PERSISTENT; segment lengths 4096
+// and 8192 of the FFT correlator, no half-bin plane): up to 64 trials of
+// mixed lengths go through ONE launch of a persistent kernel.  Per trial, the
+// real DFT and block medians run first (small launches); then the persistent
+// workgroups take tiles from a device work queue (the global tile order
+// built here): segment DFTs, correlation tiles (segment x template block),
+// harmonic-sum screen tiles, exact-sum and neighbour-test tiles.  A
+// per-trial, per-stage completion counter releases the next stage's tiles of
+// that trial, and the stages of consecutive trials are interleaved, so one
+// trial's harmonic sums run beside the next trial's correlation.  Planes,
+// codes and harmonic-sum lists live in a ring of kBatchSlots slots: trial
+// t's correlation waits until trial t - kBatchSlots has finished its
+// neighbour test.  The upload of the order, the clears, the per-trial front
+// end, the persistent launch and the copy-back of the counts are captured in
+// one HIP graph per call; candidate sorting and the copies to the host
+// follow per trial.  Every tile runs at the correlation tiles' occupancy
+// (two workgroups per CU), which slows the memory-bound harmonic-sum tiles:
+// on MI355X this form reaches about 0.6 of the two-stream rate.
 #include <algorithm>
 #include <string>
 #include <vector>

@@ -16,6 +16,7 @@ pytestmark = pytest.mark.gpu
 
 ZMAX, DZ = 100.0, 2.0
 OPTS = dict(nharm_max=16, sigma=5.0)
+PERSISTENT = dict(OPTS, batch_launch="persistent")
 
 
 def _dev(x):
@@ -46,7 +47,7 @@ def test_persistent_batch_equals_alone(gpu_lib, seg):
     lens = [1 << 18, 1 << 16, 1 << 17, 1 << 18, 1 << 15, 1 << 18, 1 << 17, 1 << 16, 1 << 18]
     trials = _trials(lens, 300)
     bank = gpu_lib.make_templates(ZMAX, DZ)
-    plan = gpu_lib.Plan(bank, 1 << 18, seg, **OPTS)
+    plan = gpu_lib.Plan(bank, 1 << 18, seg, **PERSISTENT)
     xs = [_dev(t.x) for t in trials]
     print(f"persistent batch: seg {seg}, {len(xs)} trials", flush=True)
     got = plan.search_batch(xs, caps=[200000] * len(xs))
@@ -66,7 +67,7 @@ def test_persistent_batch_trial_matches_oracle(gpu_lib):
     lens = [1 << 16, 1 << 17, 1 << 16, 1 << 15, 1 << 17]
     trials = _trials(lens, 400)
     bank = gpu_lib.make_templates(ZMAX, DZ)
-    plan = gpu_lib.Plan(bank, 1 << 17, 4096, **OPTS)
+    plan = gpu_lib.Plan(bank, 1 << 17, 4096, **PERSISTENT)
     got = plan.search_batch([_dev(t.x) for t in trials], caps=[100000] * len(trials))
     plan.close()
     bank.close()
@@ -82,7 +83,7 @@ def test_persistent_batch_two_launches(gpu_lib):
     lens = [1 << 14 if i % 2 else 1 << 15 for i in range(67)]
     trials = _trials(lens, 500)
     bank = gpu_lib.make_templates(ZMAX, DZ)
-    plan = gpu_lib.Plan(bank, 1 << 15, 4096, **OPTS)
+    plan = gpu_lib.Plan(bank, 1 << 15, 4096, **PERSISTENT)
     got = plan.search_batch([_dev(t.x) for t in trials], caps=[50000] * len(trials))
     want = _alone(gpu_lib, bank, 4096, trials, 50000)
     for i, (a, w) in enumerate(zip(got, want)):
@@ -95,7 +96,7 @@ def test_persistent_batch_two_launches(gpu_lib):
 def test_persistent_batch_overflow_reports_counts(gpu_lib):
     trials = _trials([1 << 16, 1 << 16], 600)
     bank = gpu_lib.make_templates(ZMAX, DZ)
-    plan = gpu_lib.Plan(bank, 1 << 16, 4096, **OPTS)
+    plan = gpu_lib.Plan(bank, 1 << 16, 4096, **PERSISTENT)
     xs = [_dev(t.x) for t in trials]
     full = plan.search_batch(xs, caps=[100000, 100000])
     assert len(full[0]) > 3
@@ -113,7 +114,7 @@ def test_stream_launch_equals_persistent(gpu_lib):
     trials = _trials(lens, 800)
     bank = gpu_lib.make_templates(ZMAX, DZ)
     xs = [_dev(t.x) for t in trials]
-    a = gpu_lib.Plan(bank, 1 << 17, 4096, **OPTS)
+    a = gpu_lib.Plan(bank, 1 << 17, 4096, **PERSISTENT)
     b = gpu_lib.Plan(bank, 1 << 17, 4096, batch_launch="streams", **OPTS)
     got_a = a.search_batch(xs, caps=[100000] * len(xs))
     got_b = b.search_batch(xs, caps=[100000] * len(xs))
