@@ -1,6 +1,8 @@
 // Candidate finishing on the device: order the harmonic-sum kernel's
-// (unordered) records by (nharm, k, iz) with an LSD radix sort, then write
-// the public records with r, z and the FP64 single-trial significance.
+// (unordered) records by (nharm, k, iz) with an LSD radix sort (per 8-bit
+// digit a count kernel and a scatter kernel that scans the counts itself),
+// then write the public records with r, z and the FP64 single-trial
+// significance.
 // The record count stays on the device: every kernel reads it and clamps it
 // to the buffer capacity, so nothing waits for the host in between.
 #include <hip/hip_runtime.h>
@@ -24,19 +26,40 @@ __device__ __forceinline__ uint32_t clamp_count(const uint32_t *count, uint32_t 
     return c < cap ? c : cap;
 }
 
+__device__ __forceinline__ void block_range(uint32_t n, uint32_t &beg, uint32_t &end) {
+    const uint32_t chunk = (n + RS_BLOCKS - 1) / RS_BLOCKS;
+    beg = min(n, blockIdx.x * chunk);
+    end = min(n, beg + chunk);
+}
+
+// Digit counts of a radix pass, block-major: hist[block * RS_DIGITS + digit]
+// counts the records of `block`'s range (block_range) with that digit.
+
 // key = (level nb + k) nz + iz, level = log2(nharm) in 0..4, k < nb, iz < nz:
 // ascending keys are ascending (nharm, k, iz), and all keys are below
 // 5 nb nz (32 bits, four 8-bit passes, at 2^23 samples and 201 templates).
-__global__ __launch_bounds__(256) void k_cand_keys(const DevCand *__restrict__ dc, const uint32_t *__restrict__ count,
-                                                   uint32_t cap, int64_t nb, int nz, uint64_t *__restrict__ keys,
-                                                   uint32_t *__restrict__ vals) {
+// One workgroup per block range (RS_BLOCKS of them): the keys and values of
+// the range and the first pass's digit counts of the range.
+__global__ __launch_bounds__(RS_THREADS) void k_cand_keys(const DevCand *__restrict__ dc, const uint32_t *__restrict__ count,
+                                                          uint32_t cap, int64_t nb, int nz, uint64_t *__restrict__ keys,
+                                                          uint32_t *__restrict__ vals, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t lh[RS_DIGITS];
     const uint32_t n = clamp_count(count, cap);
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int t = threadIdx.x;
+    lh[t] = 0u;
+    __syncthreads();
+    uint32_t beg, end;
+    block_range(n, beg, end);
+    for (uint32_t i = beg + t; i < end; i += RS_THREADS) {
         const DevCand c = dc[i];
         const uint64_t level = uint64_t(31 - __clz(c.nharm));
-        keys[i] = (level * uint64_t(nb) + uint64_t(uint32_t(c.k))) * uint64_t(nz) + uint64_t(uint32_t(c.iz));
+        const uint64_t key = (level * uint64_t(nb) + uint64_t(uint32_t(c.k))) * uint64_t(nz) + uint64_t(uint32_t(c.iz));
+        keys[i] = key;
         vals[i] = i;
+        atomicAdd(&lh[uint32_t(key) & (RS_DIGITS - 1u)], 1u);
     }
+    __syncthreads();
+    hist[blockIdx.x * RS_DIGITS + t] = lh[t];
 }
 
 // Lists of at most SMALL records are sorted by one workgroup in LDS
@@ -79,89 +102,60 @@ __global__ __launch_bounds__(SMALL_THREADS) void k_small_sort(const uint64_t *__
     for (uint32_t i = t; i < n; i += SMALL_THREADS) vout[i] = val[i];
 }
 
-__device__ __forceinline__ void block_range(uint32_t n, uint32_t &beg, uint32_t &end) {
-    const uint32_t chunk = (n + RS_BLOCKS - 1) / RS_BLOCKS;
-    beg = min(n, blockIdx.x * chunk);
-    end = min(n, beg + chunk);
-}
-
-// Per-block digit counts, digit-major: hist[d * RS_BLOCKS + block].
+// Digit counts of the pass at `shift` (passes after the first).
 __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *__restrict__ keys,
-                                                        const uint32_t *__restrict__ count, uint32_t cap,
-                                                        int shift, uint32_t *__restrict__ hist) {
+                                                        const uint32_t *__restrict__ count, uint32_t cap, int shift,
+                                                        uint32_t *__restrict__ hist) {
     __shared__ uint32_t lh[RS_DIGITS];
     const uint32_t n = clamp_count(count, cap);
     if (n <= SMALL) return;
     const int t = threadIdx.x;
-    lh[t] = 0;
+    lh[t] = 0u;
     __syncthreads();
     uint32_t beg, end;
     block_range(n, beg, end);
-    for (uint32_t i = beg + t; i < end; i += RS_THREADS) atomicAdd(&lh[(keys[i] >> shift) & 255u], 1u);
+    for (uint32_t i = beg + t; i < end; i += RS_THREADS) atomicAdd(&lh[uint32_t(keys[i] >> shift) & (RS_DIGITS - 1u)], 1u);
     __syncthreads();
-    hist[t * RS_BLOCKS + blockIdx.x] = lh[t];
+    hist[blockIdx.x * RS_DIGITS + t] = lh[t];
 }
 
-// Exclusive scan of the RS_DIGITS * RS_BLOCKS counts (one workgroup): each
-// thread owns 64 consecutive counts, a wave scans its threads' totals with
-// shuffles and one LDS step joins the waves.
-constexpr int SCAN_THREADS = 1024;
-constexpr int SCAN_PER = RS_DIGITS * RS_BLOCKS / SCAN_THREADS;
-static_assert(SCAN_PER % 4 == 0, "vector loads of the counts");
-__global__ __launch_bounds__(SCAN_THREADS) void k_rs_scan(uint32_t *__restrict__ hist,
-                                                          const uint32_t *__restrict__ count, uint32_t cap) {
-    __shared__ uint32_t wtot[SCAN_THREADS / 64];
-    if (clamp_count(count, cap) <= SMALL) return;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    uint4 *__restrict__ h4 = reinterpret_cast<uint4 *>(hist) + t * (SCAN_PER / 4);
-    uint4 loc[SCAN_PER / 4];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int q = 0; q < SCAN_PER / 4; ++q) {
-        loc[q] = h4[q];
-        sum += loc[q].x + loc[q].y + loc[q].z + loc[q].w;
+// One pass of the LSD radix sort: a stable scatter of one 8-bit digit.
+// Each workgroup first derives its output offsets from the pass's digit
+// counts (digit t's total over all blocks and over the blocks before this
+// one, then a scan of the totals over the digits); then it re-walks its range
+// in tiles of 256 (one element per thread, element order = wave-major lane
+// order): a lane's rank among same-digit lanes of its wave comes from 8
+// ballots, wave offsets from LDS counts, and a running per-digit offset
+// carries across tiles.
+__global__ __launch_bounds__(RS_THREADS) void k_rs_pass(const uint64_t *__restrict__ kin,
+                                                        const uint32_t *__restrict__ vin,
+                                                        const uint32_t *__restrict__ count, uint32_t cap, int shift,
+                                                        const uint32_t *__restrict__ hist, uint64_t *__restrict__ kout,
+                                                        uint32_t *__restrict__ vout) {
+    __shared__ uint32_t base[RS_DIGITS];
+    __shared__ uint32_t cnt[RS_THREADS / 64][RS_DIGITS];
+    __shared__ uint32_t wsum[RS_THREADS / 64];
+    const uint32_t n = clamp_count(count, cap);
+    if (n <= SMALL) return;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    uint32_t before = 0, total = 0;
+#pragma unroll 16
+    for (int b = 0; b < RS_BLOCKS; ++b) {
+        const uint32_t c = hist[b * RS_DIGITS + t];
+        total += c;
+        before += b < int(blockIdx.x) ? c : 0u;
     }
-    uint32_t incl = sum;
+    uint32_t incl = total;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t y = __shfl_up(incl, o);
         if (lane >= o) incl += y;
     }
-    if (lane == 63) wtot[wave] = incl;
+    if (lane == 63) wsum[w] = incl;
     __syncthreads();
-    uint32_t run = incl - sum;
-    for (int w = 0; w < wave; ++w) run += wtot[w];
-#pragma unroll
-    for (int q = 0; q < SCAN_PER / 4; ++q) {
-        uint4 o;
-        o.x = run;
-        run += loc[q].x;
-        o.y = run;
-        run += loc[q].y;
-        o.z = run;
-        run += loc[q].z;
-        o.w = run;
-        run += loc[q].w;
-        h4[q] = o;
-    }
-}
-
-// Stable scatter of one 8-bit digit.  Each block re-walks its range in tiles
-// of 256 (one element per thread, element order = wave-major lane order); a
-// lane's rank among same-digit lanes of its wave comes from 8 ballots, wave
-// offsets from LDS counts, and a running per-digit offset carries across
-// tiles.
-__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(const uint64_t *__restrict__ kin,
-                                                           const uint32_t *__restrict__ vin,
-                                                           const uint32_t *__restrict__ count, uint32_t cap,
-                                                           int shift, const uint32_t *__restrict__ hist,
-                                                           uint64_t *__restrict__ kout, uint32_t *__restrict__ vout) {
-    __shared__ uint32_t base[RS_DIGITS];
-    __shared__ uint32_t cnt[RS_THREADS / 64][RS_DIGITS];
-    const uint32_t n = clamp_count(count, cap);
-    if (n <= SMALL) return;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    base[t] = hist[t * RS_BLOCKS + blockIdx.x];
+    uint32_t off = incl - total + before;
+    for (int ww = 0; ww < w; ++ww) off += wsum[ww];
+    base[t] = off;  // ordered before its first use by the tile loop's barrier
     uint32_t beg, end;
     block_range(n, beg, end);
     const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
@@ -234,6 +228,9 @@ size_t cand_sort_scratch_bytes(uint32_t cap) {
     return size_t(cap) * (2 * sizeof(uint64_t) + 2 * sizeof(uint32_t)) + 16 + size_t(RS_DIGITS) * RS_BLOCKS * 4;
 }
 
+// Launches: keys (with the first pass's counts), the one-workgroup sort of
+// short lists, per radix pass the digit counts (after the first) and the
+// scatter (each returns at once for short lists), the public records.
 hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch, int nz,
                                     int64_t nb, int cpb, double zmax, double dz, fdas_cand *out, hipStream_t st) {
     if (cap == 0) return hipSuccess;
@@ -248,17 +245,16 @@ hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, ui
     uint32_t *hist = reinterpret_cast<uint32_t *>((reinterpret_cast<uintptr_t>(v1 + cap) + 15) & ~uintptr_t(15));
     const uint64_t blocks = (uint64_t(cap) + 255) / 256;
     const unsigned grid = unsigned(blocks < 1024 ? blocks : 1024);
-    hipLaunchKernelGGL(k_cand_keys, dim3(grid), dim3(256), 0, st, dc, count, cap, nb, nz, k0, v0);
+    hipLaunchKernelGGL(k_cand_keys, dim3(RS_BLOCKS), dim3(RS_THREADS), 0, st, dc, count, cap, nb, nz, k0, v0, hist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // the order ends in v0 after an even number of passes, else in v1
     hipLaunchKernelGGL(k_small_sort, dim3(1), dim3(SMALL_THREADS), 0, st, k0, v0, count, cap,
                        (passes % 2) ? v1 : v0);
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
-        hipLaunchKernelGGL(k_rs_hist, dim3(RS_BLOCKS), dim3(RS_THREADS), 0, st, k0, count, cap, shift, hist);
-        hipLaunchKernelGGL(k_rs_scan, dim3(1), dim3(SCAN_THREADS), 0, st, hist, count, cap);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(RS_BLOCKS), dim3(RS_THREADS), 0, st, k0, v0, count, cap, shift, hist, k1,
+        if (p > 0)
+            hipLaunchKernelGGL(k_rs_hist, dim3(RS_BLOCKS), dim3(RS_THREADS), 0, st, k0, count, cap, 8 * p, hist);
+        hipLaunchKernelGGL(k_rs_pass, dim3(RS_BLOCKS), dim3(RS_THREADS), 0, st, k0, v0, count, cap, 8 * p, hist, k1,
                            v1);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
