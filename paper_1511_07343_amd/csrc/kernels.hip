@@ -643,10 +643,10 @@ struct Group {
     uint32_t pad;
 };
 
-// Counters (six 32-bit words, zeroed before the pass): candidates; exact
-// hits; overflow flag; (unused); flagged cells (low word) and groups (high
-// word) of one 64-bit counter, so that a wave reserves both with one atomic.
-enum { CNT_CANDS = 0, CNT_HITS = 1, CNT_OVERFLOW = 2, CNT_PAIR = 4 };
+// Counters (six 32-bit words, zeroed before the pass): candidates; (unused);
+// overflow flag; (unused); flagged cells (low word) and groups (high word) of
+// one 64-bit counter, so that a wave reserves both with one atomic.
+enum { CNT_CANDS = 0, CNT_OVERFLOW = 2, CNT_PAIR = 4 };
 
 __device__ __forceinline__ uint32_t cell_count(const uint32_t *cnt) { return cnt[CNT_PAIR]; }
 __device__ __forceinline__ uint32_t group_count(const uint32_t *cnt) { return cnt[CNT_PAIR + 1]; }
@@ -843,69 +843,44 @@ __device__ __forceinline__ uint32_t cell_index(const Group &r, int i) {
 }
 
 // Pass 2, one lane per flagged cell: its exact FP32 sums, loaded from the
-// plane in the one summation order of nested_sums; cells reaching a threshold
-// at some level go to the hit list.  The workgroup iterates as a whole (256
-// cells per step) so that one atomic per step reserves the hit slots of its
-// four waves: with one atomic per wave the counter's contention made a trial
-// with strong pulsars 30 % slower.
+// plane in the one summation order of nested_sums.  No list is built: the
+// neighbour test reads every flagged cell's sums and keeps the ones that
+// reach a threshold (a hit list reserved with one atomic per workgroup step
+// cost 70 us on a trial with strong pulsars: every step of every workgroup
+// contended on the one counter).
 // Exact-sum workgroup wg of nwg (256 threads): flagged cells wg 256 + i,
 // stepping by nwg 256.
 template <int LEVELS>
-__device__ __forceinline__ void exact_tile(uint32_t wg, uint32_t nwg, const float *__restrict__ P, int nz, int64_t nb, int64_t split,
-                                               int izc, Thr thr,
-                                               const uint2 *__restrict__ blocks, uint32_t *__restrict__ cnt,
-                                               uint32_t cell_cap, float *__restrict__ sums,
-                                               uint32_t *__restrict__ hits) {
-    __shared__ uint32_t wcnt[4];
-    __shared__ uint32_t wgbase;
+__device__ __forceinline__ void exact_tile(uint32_t wg, uint32_t nwg, const float *__restrict__ P, int nz, int64_t nb,
+                                           int64_t split, int izc, const uint2 *__restrict__ blocks,
+                                           const uint32_t *__restrict__ cnt, uint32_t cell_cap,
+                                           float *__restrict__ sums) {
     const uint32_t nc = min(cell_count(cnt), cell_cap);
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const uint32_t stride = nwg * 256u;
-    // the bounds of this loop are the same for every thread of the workgroup
-    for (uint32_t base = wg * 256u; base < nc; base += stride) {
-        const uint32_t c = base + threadIdx.x;
-        bool hit = false;
-        if (c < nc) {
-            const uint2 e = blocks[c >> 1];
-            const int64_t k = 2 * int64_t(e.x) + (c & 1);
-            const int iz = int(e.y);
-            if (k < nb && iz < nz) {  // guards against entries of an overflowed list
-                float sv[5];
-                cell_sums<LEVELS>(P, nb, split, izc, iz, int(k), sv);
-                float *__restrict__ o = sums + int64_t(c) * SUM_STRIDE;
+    for (uint32_t c = wg * 256u + threadIdx.x; c < nc; c += nwg * 256u) {
+        const uint2 e = blocks[c >> 1];
+        const int64_t k = 2 * int64_t(e.x) + (c & 1);
+        const int iz = int(e.y);
+        if (k < nb && iz < nz) {  // guards against entries of an overflowed list
+            float sv[5];
+            cell_sums<LEVELS>(P, nb, split, izc, iz, int(k), sv);
+            float *__restrict__ o = sums + int64_t(c) * SUM_STRIDE;
 #pragma unroll
-                for (int l = 0; l <= LEVELS; ++l) {
-                    o[l] = sv[l];
-                    hit = hit || sv[l] >= thr.v[l];
-                }
-            }
+            for (int l = 0; l <= LEVELS; ++l) o[l] = sv[l];
         }
-        const uint64_t ballot = __ballot(hit);
-        if (lane == 0) wcnt[wave] = uint32_t(__popcll(ballot));
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const uint32_t tot = wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
-            wgbase = tot ? atomicAdd(cnt + CNT_HITS, tot) : 0u;
-        }
-        __syncthreads();
-        if (hit) {
-            uint32_t off = wgbase;
-            for (int w = 0; w < wave; ++w) off += wcnt[w];
-            hits[off + uint32_t(__popcll(ballot & ((uint64_t(1) << lane) - 1)))] = c;
-        }
-        __syncthreads();  // wcnt and wgbase are rewritten by the next step
     }
 }
 
 template <int LEVELS>
 __global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int nz, int64_t nb, int64_t split,
-                                               int izc, Thr thr,
-                                               const uint2 *__restrict__ blocks, uint32_t *__restrict__ cnt,
-                                               uint32_t cell_cap, float *__restrict__ sums,
-                                               uint32_t *__restrict__ hits) {
-    exact_tile<LEVELS>(blockIdx.x, gridDim.x, P, nz, nb, split, izc, thr, blocks, cnt, cell_cap, sums, hits);
+                                               int izc, const uint2 *__restrict__ blocks,
+                                               const uint32_t *__restrict__ cnt, uint32_t cell_cap,
+                                               float *__restrict__ sums) {
+    exact_tile<LEVELS>(blockIdx.x, gridDim.x, P, nz, nb, split, izc, blocks, cnt, cell_cap, sums);
 }
+
+// Candidate records staged in LDS by a neighbour-test workgroup before one
+// atomic reserves their slots (a step adds at most 256 x 5).
+constexpr uint32_t PK_STAGE = 1536;
 
 // Pass 3, one lane per hit: the 3x3 local maximum at every level the cell
 // reaches.  A cell keeps a level when it is strictly greater than the
@@ -914,40 +889,53 @@ __global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int 
 // not flagged has sums below every threshold, hence below the cell's, and is
 // beaten without being looked at; the others are found through the group map
 // (map entry, record, sums, issued side by side for the 8 neighbours).
-// Neighbour-test workgroup wg of nwg (256 threads): hits wg 256 + i,
-// stepping by nwg 256.
+// Neighbour-test workgroup wg of nwg (256 threads): flagged cells wg 256 + i,
+// stepping by nwg 256; stage: PK_STAGE records of LDS.  A workgroup stages
+// its candidates and reserves their slots with one atomic when the stage
+// would overflow and once at the end.
 template <int LEVELS>
 __device__ __forceinline__ void peaks_tile(uint32_t wg, uint32_t nwg, int nz, int64_t nb, Thr thr, const Group *__restrict__ groups,
                                                const uint32_t *__restrict__ group_map, const uint2 *__restrict__ blocks,
-                                               const float *__restrict__ sums, const uint32_t *__restrict__ hits,
-                                               uint32_t *__restrict__ cnt, uint32_t group_cap, uint32_t cell_cap,
-                                               DevCand *__restrict__ cands, uint32_t cap) {
+                                               const float *__restrict__ sums, uint32_t *__restrict__ cnt,
+                                               uint32_t group_cap, uint32_t cell_cap, DevCand *__restrict__ cands,
+                                               uint32_t cap, DevCand *stage) {
     __shared__ uint32_t wsum[2][4];  // per-wave candidate counts, by iteration parity
-    __shared__ uint32_t wgbase[2];
+    __shared__ uint32_t gbase;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const uint32_t nh = cnt[CNT_HITS];
+    const uint32_t nc = min(cell_count(cnt), cell_cap);
     const uint32_t ng = min(group_count(cnt), group_cap);
     const int64_t ngr = nb / SC_COLS;
-    // the workgroup iterates as a whole (256 hits per step) so that one
-    // atomic per step reserves the slots of all its candidates
+    // staged records (the same value in every thread)
+    uint32_t staged = 0;
+    auto flush = [&]() {
+        if (threadIdx.x == 0) gbase = atomicAdd(cnt + CNT_CANDS, staged);
+        __syncthreads();
+        const uint32_t g = gbase;
+        for (uint32_t i = threadIdx.x; i < staged; i += 256u)
+            if (g + i < cap) cands[g + i] = stage[i];
+        __syncthreads();  // the stage and gbase are rewritten after this
+        staged = 0;
+    };
     int par = 0;
-    for (uint32_t hw = wg * 256u; hw < nh; hw += nwg * 256u, par ^= 1) {
-        const uint32_t hidx = hw + threadIdx.x;
+    // the bounds of this loop are the same for every thread of the workgroup
+    for (uint32_t cw = wg * 256u; cw < nc; cw += nwg * 256u, par ^= 1) {
+        const uint32_t c = cw + threadIdx.x;
         uint32_t lmask = 0;  // levels still alive
         int64_t k = 0;
         int iz = 0;
         float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-        if (hidx < nh) {
-            const uint32_t c = hits[hidx];
+        if (c < nc) {
             const uint2 e = blocks[c >> 1];
             k = 2 * int64_t(e.x) + (c & 1);
             iz = int(e.y);
-            const float *__restrict__ o = sums + int64_t(c) * SUM_STRIDE;
+            if (k < nb && iz < nz) {  // the exact pass wrote no sums for other entries
+                const float *__restrict__ o = sums + int64_t(c) * SUM_STRIDE;
 #pragma unroll
-            for (int l = 0; l <= LEVELS; ++l) {
-                s[l] = o[l];
-                if (s[l] >= thr.v[l]) lmask |= 1u << l;
+                for (int l = 0; l <= LEVELS; ++l) {
+                    s[l] = o[l];
+                    if (s[l] >= thr.v[l]) lmask |= 1u << l;
+                }
             }
         }
         if (lmask != 0) {
@@ -1001,31 +989,33 @@ __device__ __forceinline__ void peaks_tile(uint32_t wg, uint32_t nwg, int nz, in
         const uint32_t ncand = __popc(lmask);
         const uint32_t incl = wave_scan(ncand, lane);
         if (lane == 63) wsum[par][wave] = incl;
+        // orders the counts, and the previous step's staged records before a flush
         __syncthreads();
-        if (threadIdx.x == 0) {
-            const uint32_t tot = wsum[par][0] + wsum[par][1] + wsum[par][2] + wsum[par][3];
-            wgbase[par] = tot ? atomicAdd(cnt + CNT_CANDS, tot) : 0u;
-        }
-        __syncthreads();
-        uint32_t slot = wgbase[par] + incl - ncand;
+        const uint32_t tot = wsum[par][0] + wsum[par][1] + wsum[par][2] + wsum[par][3];
+        if (staged + tot > PK_STAGE) flush();
+        uint32_t slot = staged + incl - ncand;
         for (int w = 0; w < wave; ++w) slot += wsum[par][w];
 #pragma unroll
         for (int l = 0; l <= LEVELS; ++l) {
-            if ((lmask >> l) & 1u) {
-                if (slot < cap) cands[slot] = DevCand{int32_t(k), iz, 1 << l, s[l]};
-                ++slot;
-            }
+            if ((lmask >> l) & 1u) stage[slot++] = DevCand{int32_t(k), iz, 1 << l, s[l]};
         }
+        staged += tot;
+    }
+    if (staged) {
+        __syncthreads();  // the last step's records are staged
+        flush();
     }
 }
 
 template <int LEVELS>
 __global__ __launch_bounds__(256) void k_peaks(int nz, int64_t nb, Thr thr, const Group *__restrict__ groups,
                                                const uint32_t *__restrict__ group_map, const uint2 *__restrict__ blocks,
-                                               const float *__restrict__ sums, const uint32_t *__restrict__ hits,
-                                               uint32_t *__restrict__ cnt, uint32_t group_cap, uint32_t cell_cap,
-                                               DevCand *__restrict__ cands, uint32_t cap) {
-    peaks_tile<LEVELS>(blockIdx.x, gridDim.x, nz, nb, thr, groups, group_map, blocks, sums, hits, cnt, group_cap, cell_cap, cands, cap);
+                                               const float *__restrict__ sums, uint32_t *__restrict__ cnt,
+                                               uint32_t group_cap, uint32_t cell_cap, DevCand *__restrict__ cands,
+                                               uint32_t cap) {
+    __shared__ DevCand stage[PK_STAGE];
+    peaks_tile<LEVELS>(blockIdx.x, gridDim.x, nz, nb, thr, groups, group_map, blocks, sums, cnt, group_cap, cell_cap,
+                       cands, cap, stage);
 }
 
 __global__ void k_zero_u32(uint32_t *__restrict__ p, int n) {
@@ -1040,7 +1030,6 @@ struct HarmLists {
     Group *groups;
     float *sums;
     uint2 *blocks;
-    uint32_t *hits;
     uint32_t *group_map;
 };
 __device__ __forceinline__ HarmLists harm_lists(void *scratch, uint32_t cell_cap, uint32_t group_cap) {
@@ -1048,8 +1037,7 @@ __device__ __forceinline__ HarmLists harm_lists(void *scratch, uint32_t cell_cap
     r.groups = static_cast<Group *>(scratch);
     r.sums = reinterpret_cast<float *>(r.groups + group_cap);
     r.blocks = reinterpret_cast<uint2 *>(r.sums + size_t(cell_cap) * SUM_STRIDE);
-    r.hits = reinterpret_cast<uint32_t *>(r.blocks + cell_cap / 2);
-    r.group_map = r.hits + cell_cap;
+    r.group_map = reinterpret_cast<uint32_t *>(r.blocks + cell_cap / 2);
     return r;
 }
 
@@ -1137,6 +1125,7 @@ __global__ __launch_bounds__(256, 2) void k_batch(BatchArgs a) {
     static_assert(corr_threads(LOG2S) == 256 && fft_threads(LOG2S) == 256, "256-thread transforms");
     static_assert(SC_WAVES * 64 == 256, "screen tiles of 256 threads");
     static_assert(Sh::LDS_FLOAT2 * 2 >= SC_WAVES * SC_TZ * 64, "screen masks fit the transform buffer");
+    static_assert(Sh::LDS_FLOAT2 * sizeof(float2) >= PK_STAGE * sizeof(DevCand), "candidates fit the transform buffer");
     __shared__ float2 lds[Sh::LDS_FLOAT2];
     __shared__ uint32_t tinfo[3];
     const int t = threadIdx.x;
@@ -1225,11 +1214,12 @@ __global__ __launch_bounds__(256, 2) void k_batch(BatchArgs a) {
                                     tr.codes, a.nz, tr.nb, a.izc, a.T, hl.groups, hl.blocks, hl.group_map, tr.cnt,
                                     a.group_cap, a.cell_cap);
             } else if (stage == BST_EXACT) {
-                exact_tile<LEVELS>(idx, kBatchExactTiles, tr.plane, a.nz, tr.nb, 0, a.izc, a.thr, hl.blocks, tr.cnt,
-                                   a.cell_cap, hl.sums, hl.hits);
+                exact_tile<LEVELS>(idx, kBatchExactTiles, tr.plane, a.nz, tr.nb, 0, a.izc, hl.blocks, tr.cnt,
+                                   a.cell_cap, hl.sums);
             } else {
                 peaks_tile<LEVELS>(idx, kBatchPeakTiles, a.nz, tr.nb, a.thr, hl.groups, hl.group_map, hl.blocks,
-                                   hl.sums, hl.hits, tr.cnt, a.group_cap, a.cell_cap, tr.cands, a.cand_cap);
+                                   hl.sums, tr.cnt, a.group_cap, a.cell_cap, tr.cands, a.cand_cap,
+                                   reinterpret_cast<DevCand *>(lds));
             }
         }
         // Every wave's stores have reached the L2 before thread 0 releases
@@ -1385,8 +1375,7 @@ hipError_t launch_correlate(const float2 *segspec, const float2 *bank, const flo
 
 size_t harmsum_scratch_bytes(int nz, int64_t nb, uint32_t cell_cap, uint32_t group_cap) {
     return size_t(group_cap) * sizeof(Group) + size_t(cell_cap) * SUM_STRIDE * sizeof(float) +
-           size_t((cell_cap + 1) / 2) * sizeof(uint2) + size_t(cell_cap) * sizeof(uint32_t) +
-           size_t(nz) * size_t(nb / SC_COLS) * sizeof(uint32_t);
+           size_t((cell_cap + 1) / 2) * sizeof(uint2) + size_t(nz) * size_t(nb / SC_COLS) * sizeof(uint32_t);
 }
 
 hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int64_t nb, int64_t split, int izc,
@@ -1409,18 +1398,17 @@ hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int6
     Group *groups = static_cast<Group *>(scratch);
     float *sums = reinterpret_cast<float *>(groups + group_cap);
     uint2 *blocks = reinterpret_cast<uint2 *>(sums + size_t(cell_cap) * SUM_STRIDE);
-    uint32_t *hits = reinterpret_cast<uint32_t *>(blocks + cell_cap / 2);
-    uint32_t *group_map = hits + cell_cap;
+    uint32_t *group_map = reinterpret_cast<uint32_t *>(blocks + cell_cap / 2);
     const int64_t rows = SC_TZ, cols = int64_t(SC_WAVE_COLS) * SC_WAVES;
     const dim3 grid1(unsigned((nb + cols - 1) / cols), unsigned((nz + rows - 1) / rows));
     const unsigned grid2 = 2048;
 #define CALL(LV)                                                                                                   \
     hipLaunchKernelGGL((k_screen<LV>), grid1, dim3(64 * SC_WAVES), 0, st, codes, nz, nb, izc, T, groups, blocks,    \
                        group_map, count, group_cap, cell_cap);                                                     \
-    hipLaunchKernelGGL((k_exact<LV>), dim3(grid2), dim3(256), 0, st, plane, nz, nb, split, izc, thr, blocks, count, \
-                       cell_cap, sums, hits);                                                                      \
+    hipLaunchKernelGGL((k_exact<LV>), dim3(grid2), dim3(256), 0, st, plane, nz, nb, split, izc, blocks, count,      \
+                       cell_cap, sums);                                                                            \
     hipLaunchKernelGGL((k_peaks<LV>), dim3(grid2), dim3(256), 0, st, nz, nb, thr, groups, group_map, blocks, sums,  \
-                       hits, count, group_cap, cell_cap, cands, cap);
+                       count, group_cap, cell_cap, cands, cap);
     switch (levels) {
         case 0: CALL(0); break;
         case 1: CALL(1); break;

@@ -82,13 +82,13 @@ hipError_t launch_corr_gemm(const uint32_t *xl, int64_t nb, int h, const void *b
 // screen's threshold in code units: it must not exceed the code sum of any
 // bin whose exact FP32 sum reaches thr[i].  Three passes: a screen of every
 // 2-bin block's bound that lists the blocks which may hold a bin reaching a
-// threshold, the exact sums of their bins from the plane (listing the bins
-// that reach one), and the neighbour test of those.  scratch:
+// threshold, the exact sums of their bins from the plane, and the neighbour
+// test of the bins whose sums reach one.  scratch:
 // harmsum_scratch_bytes(nz, nb, cell_cap, group_cap) bytes, for at most
 // cell_cap listed bins in group_cap groups of 32 columns.  count[0..5] must
 // start at 0: candidates are appended to cands (capacity cap) through
-// count[0]; count[1] counts bins reaching a threshold, count[4] and count[5]
-// listed bins and groups; count[2] is set to 1 if a list overflowed (the
+// count[0] (count[1] is not used), count[4] and count[5] count the listed
+// bins and groups; count[2] is set to 1 if a list overflowed (the
 // candidates are then incomplete).  nb (plane columns) must be a multiple of
 // 32, nz at most 65535; izc < 0 sums every harmonic in the cell's own row.
 // split > 0 marks a half-bin plane stored as two
@@ -160,7 +160,7 @@ struct BatchTrial {
     float2 *seg;
     float *plane;
     uint8_t *codes;
-    void *hits;  // harmsum_scratch_bytes layout
+    void *hits;  // harmonic-sum lists, harmsum_scratch_bytes layout
     uint32_t *cnt;  // six counters, zeroed before the launch
     DevCand *cands;
     int64_t nb;
