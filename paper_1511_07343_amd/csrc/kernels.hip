@@ -879,8 +879,9 @@ __global__ __launch_bounds__(256) void k_exact(const float *__restrict__ P, int 
 }
 
 // Candidate records staged in LDS by a neighbour-test workgroup before one
-// atomic reserves their slots (a step adds at most 256 x 5).
-constexpr uint32_t PK_STAGE = 1536;
+// atomic reserves their slots (8 KB: the workgroups of a CU stay limited by
+// their waves, not by LDS).
+constexpr uint32_t PK_STAGE = 512;
 
 // Pass 3, one lane per hit: the 3x3 local maximum at every level the cell
 // reaches.  A cell keeps a level when it is strictly greater than the
@@ -993,13 +994,30 @@ __device__ __forceinline__ void peaks_tile(uint32_t wg, uint32_t nwg, int nz, in
         __syncthreads();
         const uint32_t tot = wsum[par][0] + wsum[par][1] + wsum[par][2] + wsum[par][3];
         if (staged + tot > PK_STAGE) flush();
-        uint32_t slot = staged + incl - ncand;
+        uint32_t slot = incl - ncand;
         for (int w = 0; w < wave; ++w) slot += wsum[par][w];
+        if (tot > PK_STAGE) {
+            // a step with more records than the stage holds (up to 256 x 5)
+            // reserves and writes them directly
+            if (threadIdx.x == 0) gbase = atomicAdd(cnt + CNT_CANDS, tot);
+            __syncthreads();
+            slot += gbase;
 #pragma unroll
-        for (int l = 0; l <= LEVELS; ++l) {
-            if ((lmask >> l) & 1u) stage[slot++] = DevCand{int32_t(k), iz, 1 << l, s[l]};
+            for (int l = 0; l <= LEVELS; ++l) {
+                if ((lmask >> l) & 1u) {
+                    if (slot < cap) cands[slot] = DevCand{int32_t(k), iz, 1 << l, s[l]};
+                    ++slot;
+                }
+            }
+            __syncthreads();  // gbase is rewritten after this
+        } else {
+            slot += staged;
+#pragma unroll
+            for (int l = 0; l <= LEVELS; ++l) {
+                if ((lmask >> l) & 1u) stage[slot++] = DevCand{int32_t(k), iz, 1 << l, s[l]};
+            }
+            staged += tot;
         }
-        staged += tot;
     }
     if (staged) {
         __syncthreads();  // the last step's records are staged
