@@ -49,6 +49,7 @@ FP64 CPU oracle timed on a bounded sample of the same trial.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -724,6 +725,11 @@ def main():
     # steps read different host buffers; step i searches copy i mod 4 and
     # starts the copy of the next step's series (Sec. 4 step 1, overlapped)
     host = [torch.from_numpy(trials[0].x).pin_memory() for _ in range(HOST_COPIES)]
+    # Python's cyclic garbage collector stays off from here on: a full
+    # collection over the objects of torch and the host series took ~50 ms
+    # once in a while, inside a timed loop
+    gc.collect()
+    gc.disable()
     log(f"warmup {args.warmup}")
     for i in range(args.warmup):
         plan.search_host(host[i % HOST_COPIES], next=host[(i + 1) % HOST_COPIES], out=out)
@@ -734,7 +740,7 @@ def main():
     log(f"timed {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(args.warmup, args.warmup + args.steps):  # the warm-up staged copy warmup % 4
         s0 = time.perf_counter()
         _, nf = plan.search_host(host[i % HOST_COPIES], next=host[(i + 1) % HOST_COPIES], out=out)
         lat.append(time.perf_counter() - s0)
