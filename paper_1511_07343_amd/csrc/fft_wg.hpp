@@ -193,8 +193,12 @@ struct FftShape {
 };
 __device__ __forceinline__ int pad_idx(int i) { return i + (i >> 5); }
 
-// Per-thread twiddles of every pass, computed once (sincospif of an exact
-// binary fraction) and reused for every transform the thread takes part in.
+// Per-thread twiddles of every pass, computed once and reused for every
+// transform the thread takes part in.  Twiddle r of a pass is w^r with
+// w = exp(DIR 2 pi i jj / (Ns Rp)): the powers r = 2^b come from sincospif
+// of an exact binary fraction, every other r is one product, w^(r - 2^b)
+// times w^(2^b) for the highest bit b of r (at most log2(Rp) - 1 roundings
+// deep), which replaces Rp - 1 - log2(Rp) sincospif evaluations per pass.
 template <class Sh, int DIR>
 struct Twiddles {
     float2 w[Sh::NTW > 0 ? Sh::NTW : 1];
@@ -204,15 +208,21 @@ struct Twiddles {
             constexpr int p = decltype(pc)::value;
             constexpr int Rp = Sh::radix(p);
             constexpr int Ns = Sh::ns(p);
+            constexpr int o = Sh::tw_off(p) - 1;  // w^r at w[o + r]
             const int jj = t & (Ns - 1);
-#pragma unroll
-            for (int r = 1; r < Rp; ++r) {
-                // angle = DIR 2 pi r jj / (Ns Rp); the sincospi argument is exact
-                const float arg = float(DIR * 2 * r * jj) / float(Ns * Rp);
-                float s, c;
-                sincospif(arg, &s, &c);
-                w[Sh::tw_off(p) + (r - 1)] = make_float2(c, s);
-            }
+            static_for<1, Rp>([&](auto rc) {
+                constexpr int r = decltype(rc)::value;
+                constexpr int hb = 1 << ct_log2(r);  // highest power of two <= r
+                if constexpr (hb == r) {
+                    // angle = DIR 2 pi r jj / (Ns Rp); the sincospi argument is exact
+                    const float arg = float(DIR * 2 * r * jj) / float(Ns * Rp);
+                    float sn, c;
+                    sincospif(arg, &sn, &c);
+                    w[o + r] = make_float2(c, sn);
+                } else {
+                    w[o + r] = cmul(w[o + (r - hb)], w[o + hb]);
+                }
+            });
         });
     }
 };
