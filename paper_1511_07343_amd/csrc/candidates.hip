@@ -220,7 +220,31 @@ __global__ __launch_bounds__(256) void k_cand_finalize(const DevCand *__restrict
     }
 }
 
+// min(count, cap) records, and the six counter words, written straight into
+// page-locked host memory (device aliases), so that the host needs no round
+// trip for the count before it can copy the records.
+__global__ __launch_bounds__(256) void k_copy_records(const fdas_cand *__restrict__ src,
+                                                      const uint32_t *__restrict__ count, uint32_t cap,
+                                                      fdas_cand *__restrict__ dst, uint32_t *__restrict__ count_dst) {
+    const uint32_t n = clamp_count(count, cap);
+    const uint32_t words = n * uint32_t(sizeof(fdas_cand) / 4);
+    const uint32_t *__restrict__ s = reinterpret_cast<const uint32_t *>(src);
+    uint32_t *__restrict__ d = reinterpret_cast<uint32_t *>(dst);
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < words; i += gridDim.x * blockDim.x) d[i] = s[i];
+    if (blockIdx.x == 0 && threadIdx.x < 6) count_dst[threadIdx.x] = count[threadIdx.x];
+}
+
 }  // namespace
+
+hipError_t launch_copy_records(const fdas_cand *src, const uint32_t *count, uint32_t cap, fdas_cand *dst,
+                               uint32_t *count_dst, hipStream_t st) {
+    static_assert(sizeof(fdas_cand) % 4 == 0, "whole words");
+    const uint64_t words = uint64_t(cap) * (sizeof(fdas_cand) / 4);
+    const uint64_t blocks = (words + 255) / 256;
+    const unsigned grid = unsigned(blocks < 1024 ? (blocks > 0 ? blocks : 1) : 1024);
+    hipLaunchKernelGGL(k_copy_records, dim3(grid), dim3(256), 0, st, src, count, cap, dst, count_dst);
+    return hipGetLastError();
+}
 
 // Layout: keys k0, k1 (cap each), values v0, v1 (cap each), then the digit
 // counts at the next 16-byte boundary.

@@ -242,6 +242,23 @@ fdas_status accumulate_timing(fdas_plan_s *p) {
     return FDAS_OK;
 }
 
+// The status of a finished search from its counters in *ws.h_count (the
+// records already copied).
+static fdas_status count_status(const fdas_plan_s *p, const Workspace &ws, int64_t cap, int64_t *ncands) {
+    const uint32_t found = ws.h_count[0];
+    const bool hits_lost = ws.h_count[2] != 0;
+    if (ncands) *ncands = found;
+    if (hits_lost) {
+        set_error("harmonic-sum cell list capacity exceeded: candidates incomplete (raise cand_capacity)");
+        return FDAS_E_OVERFLOW;
+    }
+    if (int64_t(found) > cap || found > p->cand_cap) {
+        set_error("candidate capacity exceeded");
+        return FDAS_E_OVERFLOW;
+    }
+    return FDAS_OK;
+}
+
 fdas_status copy_candidates(const fdas_plan_s *p, const Workspace &ws, fdas_cand *out, int64_t cap,
                             int64_t *ncands, hipStream_t st) {
     const uint32_t found = ws.h_count[0];
@@ -329,6 +346,19 @@ void destroy_workspace(Workspace &ws) { free_workspace(ws); }
 // Candidates of a search enqueued on st: counter, then records, to the host.
 fdas_status collect(fdas_plan_s *p, Workspace &ws, fdas_cand *out, int64_t cap, int64_t *ncands,
                     hipStream_t st) {
+    // Page-locked destination: one kernel writes the records and the counters
+    // straight into host memory, with no round trip for the count in between.
+    void *dev_out = nullptr, *dev_cnt = nullptr;
+    if (cap > 0 && out && hipHostGetDevicePointer(&dev_out, out, 0) == hipSuccess && dev_out &&
+        hipHostGetDevicePointer(&dev_cnt, ws.h_count, 0) == hipSuccess && dev_cnt) {
+        const uint32_t c = uint32_t(std::min<int64_t>(cap, int64_t(p->cand_cap)));
+        hipError_t e = launch_copy_records(ws.final, ws.count, c, static_cast<fdas_cand *>(dev_out),
+                                           static_cast<uint32_t *>(dev_cnt), st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(p, e, "copy candidates");
+        return count_status(p, ws, cap, ncands);
+    }
+    (void)hipGetLastError();  // a pageable destination is not an error
     hipError_t e = hipMemcpyAsync(ws.h_count, ws.count, 24, hipMemcpyDeviceToHost, st);
     if (e != hipSuccess) return hip_fail(p, e, "copy candidate count");
     e = hipStreamSynchronize(st);

@@ -106,6 +106,10 @@ hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int6
 // to out.
 // scratch: cand_sort_scratch_bytes(cap) bytes.
 size_t cand_sort_scratch_bytes(uint32_t cap);
+// min(*count, cap) records from src to dst and count[0..5] to count_dst, both
+// destinations device aliases of page-locked host memory.
+hipError_t launch_copy_records(const fdas_cand *src, const uint32_t *count, uint32_t cap, fdas_cand *dst,
+                               uint32_t *count_dst, hipStream_t st);
 hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch, int nz,
                                     int64_t nb, int cpb, double zmax, double dz, fdas_cand *out, hipStream_t st);
 
