@@ -201,11 +201,16 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_pass(const uint64_t *__restri
     }
 }
 
+// The public records of the first min(count, cap, out_cap) sorted records;
+// with count_dst, also the six counter words there (out and count_dst may be
+// device aliases of page-locked host memory).
 __global__ __launch_bounds__(256) void k_cand_finalize(const DevCand *__restrict__ dc,
                                                        const uint32_t *__restrict__ order,
                                                        const uint32_t *__restrict__ count, uint32_t cap, int cpb,
-                                                       double zmax, double dz, fdas_cand *__restrict__ out) {
-    const uint32_t n = clamp_count(count, cap);
+                                                       double zmax, double dz, fdas_cand *__restrict__ out,
+                                                       uint32_t out_cap, uint32_t *__restrict__ count_dst) {
+    if (count_dst && blockIdx.x == 0 && threadIdx.x < 6) count_dst[threadIdx.x] = count[threadIdx.x];
+    const uint32_t n = min(clamp_count(count, cap), out_cap);
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const DevCand c = dc[order[i]];
         fdas_cand o;
@@ -256,7 +261,8 @@ size_t cand_sort_scratch_bytes(uint32_t cap) {
 // short lists, per radix pass the digit counts (after the first) and the
 // scatter (each returns at once for short lists), the public records.
 hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch, int nz,
-                                    int64_t nb, int cpb, double zmax, double dz, fdas_cand *out, hipStream_t st) {
+                                    int64_t nb, int cpb, double zmax, double dz, fdas_cand *out, hipStream_t st,
+                                    uint32_t out_cap, uint32_t *count_dst) {
     if (cap == 0) return hipSuccess;
     const uint64_t span = 5 * uint64_t(nb) * uint64_t(nz);  // keys are below this
     int bits = 1;
@@ -289,7 +295,8 @@ hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, ui
         v0 = v1;
         v1 = tv;
     }
-    hipLaunchKernelGGL(k_cand_finalize, dim3(grid), dim3(256), 0, st, dc, v0, count, cap, cpb, zmax, dz, out);
+    hipLaunchKernelGGL(k_cand_finalize, dim3(grid), dim3(256), 0, st, dc, v0, count, cap, cpb, zmax, dz, out, out_cap,
+                       count_dst);
     return hipGetLastError();
 }
 

@@ -125,9 +125,19 @@ void destroy_workspace(Workspace &ws);
 // state alone; X_out / med_out (may be NULL) receive the normalised
 // spectrum's source buffer and medians the search used (NULL for a
 // time-domain plan, medians NULL for an already normalised spectrum).
+// direct (may be NULL): the public records go to direct->out (at most
+// direct->cap of them) and the counters to direct->count instead of
+// ws.final (device aliases of page-locked host memory; FFT and matrix
+// plans without refinement only).
+struct DirectOut {
+    fdas_cand *out;
+    uint32_t cap;
+    uint32_t *count;
+};
 fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &g, int32_t in_kind,
                            const void *in_dev, float *plane, DevCand *dcands, uint32_t *dcount, hipStream_t st,
-                           bool timed = false, const float2 **X_out = nullptr, const double **med_out = nullptr);
+                           bool timed = false, const float2 **X_out = nullptr, const double **med_out = nullptr,
+                           const DirectOut *direct = nullptr);
 // Trial value of plane row iz: the drift z(iz) of a template plan, the
 // acceleration trial alpha_iz of a time-domain plan.
 double row_value(const fdas_plan_s *p, int32_t iz);

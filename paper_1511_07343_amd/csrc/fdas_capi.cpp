@@ -163,7 +163,8 @@ double row_value(const fdas_plan_s *p, int32_t iz) {
 
 fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &g, int32_t in_kind,
                            const void *in_dev, float *plane, DevCand *dcands, uint32_t *dcount,
-                           hipStream_t st, bool timed, const float2 **X_out, const double **med_out) {
+                           hipStream_t st, bool timed, const float2 **X_out, const double **med_out,
+                           const DirectOut *direct) {
     if (X_out) *X_out = nullptr;
     if (med_out) *med_out = nullptr;
     if (p->td) return enqueue_td_search(p, ws, g, in_kind, in_dev, plane, dcands, dcount, st, timed);
@@ -214,8 +215,14 @@ fdas_status enqueue_search(fdas_plan_s *p, const Workspace &ws, const Geometry &
     e = launch_harmsum(plane, ws.codes, p->nz, g.ncol, p->opts.interbin ? g.nb : 0, p->izc, p->opts.nharm_max, p->thr_f, p->code_thr, ws.hits,
                        p->hit_cap, p->group_cap, dcands, dcount, p->cand_cap, st);
     if (e != hipSuccess) return hip_fail(p, e, "harmonic sum");
-    e = launch_finish_candidates(dcands, dcount, p->cand_cap, ws.sort, p->nz, g.ncol, cols_per_bin(p), p->zmax, p->dz,
-                                 ws.final, st);
+    if (direct && (p->td || p->opts.refine_levels > 0)) {
+        set_error("records written to the host directly need a plan without refinement");
+        return FDAS_E_INVAL;
+    }
+    e = direct ? launch_finish_candidates(dcands, dcount, p->cand_cap, ws.sort, p->nz, g.ncol, cols_per_bin(p), p->zmax,
+                                          p->dz, direct->out, st, direct->cap, direct->count)
+               : launch_finish_candidates(dcands, dcount, p->cand_cap, ws.sort, p->nz, g.ncol, cols_per_bin(p), p->zmax,
+                                          p->dz, ws.final, st);
     if (e != hipSuccess) return hip_fail(p, e, "candidate sort");
     if ((e = mark(5)) != hipSuccess) return hip_fail(p, e, "timing event");
     if (p->opts.refine_levels > 0) {
@@ -776,13 +783,33 @@ fdas_status fdas_search(fdas_plan_t *plan, int32_t in_kind, const void *in_dev, 
     plan->searched = false;
     plan->last_X = nullptr;
     plan->last_med = nullptr;
-    fdas_status s = enqueue_search(plan, ws, g, in_kind, in_dev, plane, ws.cands, ws.count, st, timed, &X, &med);
+    // Page-locked destination and nothing to post-process: the finishing
+    // kernel writes the records and the counters straight into host memory.
+    DirectOut direct{};
+    bool use_direct = false;
+    if (cap > 0 && !plan->td && plan->opts.refine_levels == 0) {
+        void *dev_out = nullptr, *dev_cnt = nullptr;
+        if (hipHostGetDevicePointer(&dev_out, cands_host, 0) == hipSuccess && dev_out &&
+            hipHostGetDevicePointer(&dev_cnt, ws.h_count, 0) == hipSuccess && dev_cnt) {
+            direct = DirectOut{static_cast<fdas_cand *>(dev_out), uint32_t(std::min<int64_t>(cap, plan->cand_cap)),
+                               static_cast<uint32_t *>(dev_cnt)};
+            use_direct = true;
+        }
+        (void)hipGetLastError();  // a pageable destination is not an error
+    }
+    fdas_status s = enqueue_search(plan, ws, g, in_kind, in_dev, plane, ws.cands, ws.count, st, timed, &X, &med,
+                                   use_direct ? &direct : nullptr);
     if (s != FDAS_OK) return s;
     plan->last_X = X;
     plan->last_med = med;
     plan->last_nb = g.nb;
     plan->searched = true;
-    s = collect(plan, ws, cands_host, cap, ncands, st);
+    if (use_direct) {
+        const hipError_t e = hipStreamSynchronize(st);
+        s = e != hipSuccess ? hip_fail(plan, e, "search") : count_status(plan, ws, cap, ncands);
+    } else {
+        s = collect(plan, ws, cands_host, cap, ncands, st);
+    }
     if (timed && (s == FDAS_OK || s == FDAS_E_OVERFLOW)) {
         const fdas_status t = accumulate_timing(plan);
         if (t != FDAS_OK) return t;

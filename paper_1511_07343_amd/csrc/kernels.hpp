@@ -100,18 +100,21 @@ hipError_t launch_harmsum(const float *plane, const uint8_t *codes, int nz, int6
                           const float *thr_host, const uint32_t *code_thr, void *scratch, uint32_t cell_cap,
                           uint32_t group_cap, DevCand *cands, uint32_t *count, uint32_t cap, hipStream_t st);
 
-// Candidate finishing: sort the first min(*count, cap) records by
-// (nharm, k, iz) (k < nb plane columns, iz < nz) and write public records
-// (r = k / (nharm cpb) with cpb plane columns per bin, z, FP64 significance)
-// to out.
-// scratch: cand_sort_scratch_bytes(cap) bytes.
-size_t cand_sort_scratch_bytes(uint32_t cap);
 // min(*count, cap) records from src to dst and count[0..5] to count_dst, both
 // destinations device aliases of page-locked host memory.
 hipError_t launch_copy_records(const fdas_cand *src, const uint32_t *count, uint32_t cap, fdas_cand *dst,
                                uint32_t *count_dst, hipStream_t st);
+// Candidate finishing: sort the first min(*count, cap) records by
+// (nharm, k, iz) (k < nb plane columns, iz < nz) and write the first
+// min(*count, cap, out_cap) of them as public records (r = k / (nharm cpb)
+// with cpb plane columns per bin, z, FP64 significance) to out; with
+// count_dst, also count[0..5] there (out and count_dst may be device aliases
+// of page-locked host memory).
+// scratch: cand_sort_scratch_bytes(cap) bytes.
+size_t cand_sort_scratch_bytes(uint32_t cap);
 hipError_t launch_finish_candidates(const DevCand *dc, const uint32_t *count, uint32_t cap, void *scratch, int nz,
-                                    int64_t nb, int cpb, double zmax, double dz, fdas_cand *out, hipStream_t st);
+                                    int64_t nb, int cpb, double zmax, double dz, fdas_cand *out, hipStream_t st,
+                                    uint32_t out_cap = 0xffffffffu, uint32_t *count_dst = nullptr);
 
 // De-dispersion: out[i][t] = sum_c fil[c][t + delays[i][c]] for t < nout
 // (channel-major 8-bit filterbank, nchan x nsamp; exact integer sums stored
