@@ -125,3 +125,26 @@ def test_stream_launch_equals_persistent(gpu_lib):
     a.close()
     b.close()
     bank.close()
+
+
+def test_stream_batch_into_page_locked_buffer(gpu_lib):
+    # the default launch form with a page-locked record buffer returns what it
+    # copies into pageable memory; a capacity below a trial's count reports
+    # OVERFLOW
+    lens = [1 << 16, 1 << 15, 1 << 16, 1 << 16, 1 << 15]
+    trials = _trials(lens, 900)
+    bank = gpu_lib.make_templates(ZMAX, DZ)
+    xs = [_dev(t.x) for t in trials]
+    plan = gpu_lib.Plan(bank, 1 << 16, 4096, **OPTS)
+    caps = [100000] * len(xs)
+    ref = plan.search_batch(xs, caps=caps)
+    assert len(ref[0]) > 3
+    got = plan.search_batch(xs, caps=caps, out=gpu_lib.pinned_candidates(sum(caps)))
+    for i, (a, b) in enumerate(zip(got, ref)):
+        assert np.array_equal(a, b), i
+    small = [3] + caps[1:]
+    with pytest.raises(gpu_lib.FdasError) as e:
+        plan.search_batch(xs, caps=small, out=gpu_lib.pinned_candidates(sum(small)))
+    assert e.value.status == -4
+    plan.close()
+    bank.close()

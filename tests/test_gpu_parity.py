@@ -271,15 +271,27 @@ def test_autotune_and_cache(gpu_lib, tmp_path):
 
 
 def test_pinned_output_buffer(gpu_lib):
+    # records written into page-locked memory by the device (straight from the
+    # finishing kernel, or by the copy kernel after refinement) equal the ones
+    # copied into pageable memory; a capacity below the count reports
+    # OVERFLOW with the true count and the first records in order
     t = synth.make_series(1 << 15, seed=71)
     bank = gpu_lib.make_templates(10.0, 2.0)
-    plan = gpu_lib.Plan(bank, 1 << 15, 256, nharm_max=4, sigma=3.0, median_window=256)
     x = _dev(t.x)
-    ref, n = plan.search(x)
-    out = gpu_lib.pinned_candidates(1 << 16)
-    got, n2 = plan.search(x, out=out)
-    assert n2 == n and np.array_equal(got, ref)
-    plan.close()
+    for levels in (0, 2):
+        plan = gpu_lib.Plan(bank, 1 << 15, 256, nharm_max=4, sigma=3.0, median_window=256, refine_levels=levels)
+        ref, n = plan.search(x)
+        assert n > 8
+        out = gpu_lib.pinned_candidates(1 << 16)
+        got, n2 = plan.search(x, out=out)
+        assert n2 == n and np.array_equal(got, ref)
+        small = gpu_lib.pinned_candidates(5)
+        with pytest.raises(gpu_lib.FdasError) as e:
+            plan.search(x, out=small, cap=5)
+        assert e.value.status == -4
+        got, n3 = plan.search(x, out=small, cap=5, allow_overflow=True)
+        assert n3 == n and np.array_equal(got, ref[:5])
+        plan.close()
     bank.close()
 
 
