@@ -228,10 +228,14 @@ struct Twiddles {
 };
 
 // The transform.  v: registers in strided layout (see top); lds: workgroup
-// buffer of Sh::LDS_FLOAT2 float2.  The caller must not touch lds between
-// the call's first write and its return.  On return every thread has passed
-// a barrier after its last LDS read, so lds may be reused at once.
-template <class Sh, int DIR>
+// buffer of Sh::LDS_FLOAT2 float2 (SPLIT: of Sh::LDS_FLOAT2 floats).  The
+// caller must not touch lds between the call's first write and its return.
+// On return every thread has passed a barrier after its last LDS read, so lds
+// may be reused at once.
+// SPLIT: a pass keeps its outputs in registers and exchanges the real parts,
+// then the imaginary parts, through half the LDS (two more barriers per
+// exchange); the values and so the results are those of the one-round form.
+template <class Sh, int DIR, bool SPLIT = false>
 __device__ __forceinline__ void fft_wg(float2 (&v)[Sh::R], float2 *lds, const Twiddles<Sh, DIR> &tw,
                                        int t) {
     static_for<0, Sh::NPASS>([&](auto pc) {
@@ -253,7 +257,8 @@ __device__ __forceinline__ void fft_wg(float2 (&v)[Sh::R], float2 *lds, const Tw
                 });
             }
             dft_reg<Rp, DIR>(u);
-            if constexpr (last) {
+            if constexpr (last || SPLIT) {
+                // (SPLIT: output r of butterfly b waits in its input's register)
 #pragma unroll
                 for (int r = 0; r < Rp; ++r) v[b + r * nb] = u[r];
             } else {
@@ -263,11 +268,30 @@ __device__ __forceinline__ void fft_wg(float2 (&v)[Sh::R], float2 *lds, const Tw
                 for (int r = 0; r < Rp; ++r) lds[pad_idx(base + r * Ns)] = u[r];
             }
         });
-        if constexpr (!last) {
+        if constexpr (!last && !SPLIT) {
             __syncthreads();
 #pragma unroll
             for (int m = 0; m < Sh::R; ++m) v[m] = lds[pad_idx(t + Sh::NT * m)];
             __syncthreads();
+        } else if constexpr (!last) {
+            float *__restrict__ lf = reinterpret_cast<float *>(lds);
+            static_for<0, 2>([&](auto hc) {
+                constexpr int half = decltype(hc)::value;
+                static_for<0, nb>([&](auto bc) {
+                    constexpr int b = decltype(bc)::value;
+                    const int j = t + Sh::NT * b;
+                    const int base = (j / Ns) * Ns * Rp + (j & (Ns - 1));
+#pragma unroll
+                    for (int r = 0; r < Rp; ++r) lf[pad_idx(base + r * Ns)] = half ? v[b + r * nb].y : v[b + r * nb].x;
+                });
+                __syncthreads();
+#pragma unroll
+                for (int m = 0; m < Sh::R; ++m) {
+                    const float q = lf[pad_idx(t + Sh::NT * m)];
+                    if constexpr (half) v[m].y = q; else v[m].x = q;
+                }
+                __syncthreads();
+            });
         }
     });
 }

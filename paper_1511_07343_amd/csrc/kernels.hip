@@ -344,7 +344,7 @@ __global__ __launch_bounds__(kMedThreads) void k_median(const float2 *__restrict
 // -------------------------------------------------------- segment DFTs
 // Segment s (one workgroup of fft_threads(LOG2S) threads, lds holding
 // FftShape::LDS_FLOAT2 float2): DFT of Xhat[s L - h + n], n in [0, S).
-template <int LOG2S>
+template <int LOG2S, bool SPLIT = false>
 __device__ __forceinline__ void segfft_item(float2 *lds, int t, const float2 *__restrict__ X,
                                             const double *__restrict__ med, int W, int64_t nb, int h, int64_t s,
                                             float2 *__restrict__ segspec) {
@@ -369,7 +369,7 @@ __device__ __forceinline__ void segfft_item(float2 *lds, int t, const float2 *__
         }
         v[m] = x;
     }
-    fft_wg<Sh, -1>(v, lds, tw, t);
+    fft_wg<Sh, -1, SPLIT>(v, lds, tw, t);
 #pragma unroll
     for (int m = 0; m < Sh::R; ++m) segspec[s * Sh::S + t + Sh::NT * m] = v[m];
 }
@@ -380,8 +380,13 @@ __global__ __launch_bounds__(fft_threads(LOG2S)) void k_segfft(const float2 *__r
                                                                int W, int64_t nb, int h,
                                                                float2 *__restrict__ segspec) {
     using Sh = FftShape<LOG2S, fft_threads(LOG2S)>;
-    __shared__ float2 lds[Sh::LDS_FLOAT2];
-    segfft_item<LOG2S>(lds, threadIdx.x, X, med, W, nb, h, blockIdx.x, segspec);
+    // From 8192 points the one-round exchange (S float2 of LDS) would hold a
+    // compute unit to two workgroups, fewer than its registers allow, and
+    // the 527 segments of a 2^23-sample series would take two rounds of
+    // workgroups: exchange the halves through S floats instead.
+    constexpr bool kSplit = LOG2S >= 13;
+    __shared__ float2 lds[kSplit ? (Sh::LDS_FLOAT2 + 1) / 2 : Sh::LDS_FLOAT2];
+    segfft_item<LOG2S, kSplit>(lds, threadIdx.x, X, med, W, nb, h, blockIdx.x, segspec);
 }
 
 // Xhat = X sqrt(ln2 / m(k)) written out (inspection only; the search path
