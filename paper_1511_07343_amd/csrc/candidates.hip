@@ -20,6 +20,7 @@ namespace {
 constexpr int RS_BLOCKS = 128;   // workgroups of the histogram and scatter passes
 constexpr int RS_THREADS = 256;  // four waves
 constexpr int RS_DIGITS = 256;   // 8-bit digits
+constexpr int RS_AHEAD = 8;      // tiles of 256 records a scatter workgroup loads at once
 
 __device__ __forceinline__ uint32_t clamp_count(const uint32_t *count, uint32_t cap) {
     const uint32_t c = *count;
@@ -114,7 +115,18 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *__restri
     __syncthreads();
     uint32_t beg, end;
     block_range(n, beg, end);
-    for (uint32_t i = beg + t; i < end; i += RS_THREADS) atomicAdd(&lh[uint32_t(keys[i] >> shift) & (RS_DIGITS - 1u)], 1u);
+    for (uint32_t batch = beg; batch < end; batch += RS_AHEAD * RS_THREADS) {
+        uint64_t kk[RS_AHEAD];
+#pragma unroll
+        for (int q = 0; q < RS_AHEAD; ++q) {
+            const uint32_t i = batch + uint32_t(q) * RS_THREADS + t;
+            kk[q] = i < end ? keys[i] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < RS_AHEAD; ++q)
+            if (batch + uint32_t(q) * RS_THREADS + t < end)
+                atomicAdd(&lh[uint32_t(kk[q] >> shift) & (RS_DIGITS - 1u)], 1u);
+    }
     __syncthreads();
     hist[blockIdx.x * RS_DIGITS + t] = lh[t];
 }
@@ -159,45 +171,56 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_pass(const uint64_t *__restri
     uint32_t beg, end;
     block_range(n, beg, end);
     const uint64_t lt_mask = (uint64_t(1) << lane) - 1;
-    for (uint32_t tile = beg; tile < end; tile += RS_THREADS) {
+    // RS_AHEAD tiles' keys and values are loaded together, so that the
+    // tiles of a batch wait for memory once
+    for (uint32_t batch = beg; batch < end; batch += RS_AHEAD * RS_THREADS) {
+        uint64_t kk[RS_AHEAD];
+        uint32_t vv[RS_AHEAD];
 #pragma unroll
-        for (int ww = 0; ww < RS_THREADS / 64; ++ww) cnt[ww][t] = 0;
-        __syncthreads();
-        const uint32_t i = tile + t;
-        const bool valid = i < end;
-        uint64_t key = 0;
-        uint32_t val = 0, d = 0;
-        if (valid) {
-            key = kin[i];
-            val = vin[i];
-            d = uint32_t(key >> shift) & 255u;
+        for (int q = 0; q < RS_AHEAD; ++q) {
+            const uint32_t i = batch + uint32_t(q) * RS_THREADS + t;
+            kk[q] = i < end ? kin[i] : 0;
+            vv[q] = i < end ? vin[i] : 0u;
         }
-        uint64_t peers = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1u;
-            const uint64_t m = __ballot(valid && bit);
-            peers &= bit ? m : ~m;
-        }
-        const uint32_t rank = __popcll(peers & lt_mask);
-        if (valid && rank == 0) cnt[w][d] = __popcll(peers);
-        __syncthreads();
-        // thread t owns digit t: offsets of each wave within the tile
-        uint32_t o = 0;
+        for (int q = 0; q < RS_AHEAD; ++q) {
+            const uint32_t tile = batch + uint32_t(q) * RS_THREADS;
+            if (tile >= end) break;  // the same for every thread
 #pragma unroll
-        for (int ww = 0; ww < RS_THREADS / 64; ++ww) {
-            const uint32_t c = cnt[ww][t];
-            cnt[ww][t] = o;
-            o += c;
+            for (int ww = 0; ww < RS_THREADS / 64; ++ww) cnt[ww][t] = 0;
+            __syncthreads();
+            const uint32_t i = tile + t;
+            const bool valid = i < end;
+            const uint64_t key = kk[q];
+            const uint32_t val = vv[q];
+            const uint32_t d = valid ? uint32_t(key >> shift) & 255u : 0u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t m = __ballot(valid && bit);
+                peers &= bit ? m : ~m;
+            }
+            const uint32_t rank = __popcll(peers & lt_mask);
+            if (valid && rank == 0) cnt[w][d] = __popcll(peers);
+            __syncthreads();
+            // thread t owns digit t: offsets of each wave within the tile
+            uint32_t o = 0;
+#pragma unroll
+            for (int ww = 0; ww < RS_THREADS / 64; ++ww) {
+                const uint32_t c = cnt[ww][t];
+                cnt[ww][t] = o;
+                o += c;
+            }
+            __syncthreads();
+            if (valid) {
+                const uint32_t pos = base[d] + cnt[w][d] + rank;
+                kout[pos] = key;
+                vout[pos] = val;
+            }
+            __syncthreads();
+            base[t] += o;
         }
-        __syncthreads();
-        if (valid) {
-            const uint32_t pos = base[d] + cnt[w][d] + rank;
-            kout[pos] = key;
-            vout[pos] = val;
-        }
-        __syncthreads();
-        base[t] += o;
     }
 }
 
