@@ -12,15 +12,19 @@ sorted candidates to page-locked host memory.
 
 Prints one JSON line: that plain per-trial rate as ``value`` (and, as
 ``plain_resident``, the same loop with the series already in HBM), then
+  plain_autotuned  the same loop with the segment length and templates per
+             block the autotuner picks (fdas_autotune: 1024- to 8192-point
+             segments) instead of the named 8192;
   batched    64 distinct trials of 2^23 samples (0-3 pulsars each) through
              fdas_search_batch (graph-captured launches, autotuned segment
-             length and templates per block), series resident in HBM, and
+             length and templates per block; the persistent form at its own
+             tuned shape, 4096 or 8192 points), series resident in HBM, and
              again with the series copied from page-locked host memory
              (PCIe included; the next call's copies overlap the current
              call);
   served     the 6000-request trace (20/30/50 % of 2^21/2^22/2^23 samples,
              Poisson arrivals filling 530 s, 5 % with a pulsar) replayed
-             through the continuous-batching server from host memory (PCIe
+             through the continuous-batching server (autotuned shape) from host memory (PCIe
              included): saturated (a bounded number in flight) for
              throughput, and the first requests at their arrival times,
              compressed 10x, for p50/p99 latency;
@@ -165,7 +169,7 @@ STAGE_STEPS = 20    # searches of the trial timed stage by stage with HIP events
 C4_LENGTHS = (1 << 21, 1 << 22, 1 << 23)
 
 
-def bench_batched(fdas, bank, xs, per_call: int, host=None):
+def bench_batched(fdas, bank, xs, per_call: int, tuned, tuned_p, host=None):
     """64 distinct trials through fdas_search_batch, per_call trials per call,
     the series resident in HBM, in both launch forms: the default (per-trial
     graphs on two streams) and the persistent kernel (one launch per call of
@@ -175,12 +179,14 @@ def bench_batched(fdas, bank, xs, per_call: int, host=None):
     overlapping the previous call's search on a second stream."""
     import numpy as np
     import torch
-    seg_b, tpb_b, tune_ms = fdas.autotune(bank, N, nharm_max=NHARM, sigma=SIGMA)
-    log(f"batched: {len(xs)} trials, {per_call} per call, segment {seg_b}, {tpb_b} templates per block")
+    seg_b, tpb_b, tune_ms = tuned
+    seg_p, tpb_p, tune_p = tuned_p
+    log(f"batched: {len(xs)} trials, {per_call} per call, segment {seg_b}, {tpb_b} templates per block "
+        f"(persistent form: {seg_p}, {tpb_p})")
     bcap = 1 << 19
     bout = fdas.pinned_candidates(bcap * per_call)
-    # the persistent kernel first
-    plans = fdas.Plan(bank, N, seg_b, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb_b,
+    # the persistent kernel first, at the shape tuned over its own segment lengths
+    plans = fdas.Plan(bank, N, seg_p, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb_p,
                       batch_launch="persistent")
     ref = [c.copy() for c in plans.search_batch(xs[:per_call], caps=[bcap] * per_call, out=bout)]
     torch.cuda.synchronize()
@@ -192,13 +198,18 @@ def bench_batched(fdas, bank, xs, per_call: int, host=None):
     ts = time.perf_counter() - t0
     plans.close()
     persistent = {"value": round(len(xs) / ts, 3), "unit": "DM trials/s", "ms_per_trial": round(1e3 * ts / len(xs), 4),
-                  "launch": ("one persistent-kernel launch per call of up to 64 trials "
-                             "(fdas_opts.batch_launch = FDAS_BATCH_PERSISTENT)") if seg_b in (4096, 8192)
-                            else "per-trial graphs on two streams (no persistent form at this segment length)"}
+                  "segment": seg_p, "templates_per_block": tpb_p,
+                  "segment_dft_plus_correlate_ms": round(tune_p, 4),
+                  "launch": "one persistent-kernel launch per call of up to 64 trials "
+                            "(fdas_opts.batch_launch = FDAS_BATCH_PERSISTENT)"}
+    # the default form at the persistent form's shape gives the same records
+    chk = fdas.Plan(bank, N, seg_p, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb_p)
+    got_p = chk.search_batch(xs[:per_call], caps=[bcap] * per_call, out=bout)
+    persistent["same_records_as_default"] = all(np.array_equal(a, b) for a, b in zip(got_p, ref))
+    chk.close()
     planb = fdas.Plan(bank, N, seg_b, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb_b)
     got = planb.search_batch(xs[:per_call], caps=[bcap] * per_call, out=bout)  # allocates
     counts = [len(c) for c in got]
-    persistent["same_records_as_default"] = all(np.array_equal(a, b) for a, b in zip(got, ref))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(0, len(xs), per_call):
@@ -319,13 +330,37 @@ def _replay(fdas, srv, trace, ring, paced_speedup, inflight):
     return time.perf_counter() - t0, np.asarray(lat), found, kept
 
 
-def bench_served(fdas, bank, ring, requests: int, paced: int, speedup: float):
+def bench_plain_tuned(fdas, bank, host, out_buf, steps: int, seg: int, tpb: int):
+    """The headline's plain loop (fdas_search_host per trial: the series
+    copied from page-locked host memory, the next copy overlapping the search,
+    the records to page-locked memory) with the segment length and templates
+    per block the autotuner picked instead of the named 8192-bin segments."""
+    import torch
+    plan = fdas.Plan(bank, N, seg, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb)
+    for i in range(3):
+        plan.search_host(host[i % HOST_COPIES], next=host[(i + 1) % HOST_COPIES], out=out_buf)
+    counts = set()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(3, 3 + steps):
+        _, nf = plan.search_host(host[i % HOST_COPIES], next=host[(i + 1) % HOST_COPIES], out=out_buf)
+        counts.add(nf)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    plan.close()
+    return {"value": round(steps / t, 3), "unit": "DM trials/s", "steps": steps, "ms_per_step": round(1e3 * t / steps, 4),
+            "segment": seg, "templates_per_block": tpb, "candidates_per_trial": sorted(counts),
+            "data": "the headline's trial and loop (PCIe included) at the autotuned shape"}
+
+
+def bench_served(fdas, bank, ring, requests: int, paced: int, speedup: float, seg: int, tpb: int):
     """The served trace: saturated replay (throughput) and a paced replay of
-    its first `paced` requests at `speedup` x real time (latency)."""
+    its first `paced` requests at `speedup` x real time (latency), with the
+    autotuned segment length and templates per block."""
     import numpy as np
     import synth
     trace = synth.served_trace()[:requests]
-    srv = fdas.Server(bank, SEG, N, max_slots=4, nharm_max=NHARM, sigma=SIGMA)
+    srv = fdas.Server(bank, seg, N, max_slots=4, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb)
     srv.submit(ring[N][1], tag=1 << 40)  # warm the buffers of the longest length
     srv.poll(timeout_ms=120000)
     log(f"served: saturated replay of {len(trace)} requests")
@@ -336,12 +371,13 @@ def bench_served(fdas, bank, ring, requests: int, paced: int, speedup: float):
     import torch
     same = {}
     for n, recs in sorted(kept.items()):
-        pl = fdas.Plan(bank, n, SEG, nharm_max=NHARM, sigma=SIGMA)
+        pl = fdas.Plan(bank, n, seg, nharm_max=NHARM, sigma=SIGMA, templates_per_block=tpb)
         want, _ = pl.search(torch.from_numpy(ring[n][0]).cuda())
         pl.close()
         same[str(n)] = {"candidates": int(len(recs)), "equal_alone": bool(np.array_equal(recs, want))}
     mean_bytes = sum(path_bytes(e["nsamp"], bank.nz) for e in trace) / len(trace)
     out = {"value": round(len(trace) / ts, 3), "unit": "DM trials/s", "requests": len(trace),
+           "segment": seg, "templates_per_block": tpb,
            "path_roofline": path_roofline(mean_bytes, len(trace) / ts),
            "mix": "20/30/50 % of 2^21/2^22/2^23 samples, 5 % with a pulsar",
            "arrival": "saturated: next request submitted while 8 are in flight; host series, PCIe included",
@@ -793,6 +829,15 @@ def main():
     }
     log("plain search with the series resident in HBM")
     out["plain_resident"] = bench_plain_resident(plan, xs[0], pinned, min(args.steps, 50))
+    tuned = tuned_p = None
+    if extra:
+        # segment length and templates per block for the batched and served
+        # forms (and the persistent launch, over its own lengths)
+        tuned = fdas.autotune(bank, N, nharm_max=NHARM, sigma=SIGMA)
+        tuned_p = fdas.autotune(bank, N, nharm_max=NHARM, sigma=SIGMA, batch_launch="persistent")
+        log(f"autotuned shape {tuned[0]}-point segments, {tuned[1]} templates per block; plain loop at it")
+        out["plain_autotuned"] = bench_plain_tuned(fdas, bank, host, pinned, min(args.steps, 50), tuned[0], tuned[1])
+        out["plain_autotuned"]["segment_dft_plus_correlate_ms"] = round(tuned[2], 4)
 
     if extra:
         log("small configuration latency")
@@ -814,13 +859,13 @@ def main():
 
     if batch_host:
         bxs = [torch.from_numpy(x).to(dev) for x in batch_host]
-        out["batched"] = bench_batched(fdas, bank, bxs, args.batch, host=batch_host)
+        out["batched"] = bench_batched(fdas, bank, bxs, args.batch, tuned, tuned_p, host=batch_host)
         del batch_host
         del bxs
     plan.close()
 
     if ring:
-        out["served"] = bench_served(fdas, bank, ring, args.served, args.paced, args.speedup)
+        out["served"] = bench_served(fdas, bank, ring, args.served, args.paced, args.speedup, tuned[0], tuned[1])
 
     if extra and args.precision_trials > 0:
         log("precision variant: FFT FP32 vs BF16 / FP16 matrix correlators")

@@ -67,9 +67,13 @@ extern "C" fdas_status fdas_autotune(const fdas_bank *bank, int64_t nsamp, const
     if (st != FDAS_OK) return st;
     st = check_nsamp(nsamp, 0, bank->h);
     if (st != FDAS_OK) return st;
-    char keybuf[160];
-    std::snprintf(keybuf, sizeof(keybuf), "%s nsamp=%lld nz=%d h=%d", arch_name().c_str(), (long long)nsamp,
-                  bank->nz, bank->h);
+    // The persistent batch launch runs 4096- and 8192-point segments only;
+    // every other form takes any power of two from 1024 up (and >= 4 h).
+    const bool persistent = o.batch_launch == FDAS_BATCH_PERSISTENT;
+    const int32_t seg_lo = persistent ? 4096 : 1024;
+    char keybuf[192];
+    std::snprintf(keybuf, sizeof(keybuf), "%s nsamp=%lld nz=%d h=%d segs=%d-8192", arch_name().c_str(),
+                  (long long)nsamp, bank->nz, bank->h, seg_lo);
     const std::string key(keybuf);
     double ms_cached = 0.0;
     if (cache_lookup(cache_path, key, seg_out, tpb_out, &ms_cached)) {
@@ -98,8 +102,7 @@ extern "C" fdas_status fdas_autotune(const fdas_bank *bank, int64_t nsamp, const
     int64_t best_nwg = 0;
     const int32_t tpbs[] = {7, 13, 26};
     std::vector<fdas_cand> cands(1);
-    // the segment lengths of the persistent batch launch
-    for (int32_t seg = 4096; seg <= 8192; seg *= 2) {
+    for (int32_t seg = seg_lo; seg <= 8192; seg *= 2) {
         if (seg < 4 * bank->h) continue;
         fdas_plan_t *p = nullptr;
         st = fdas_plan(bank, nsamp, seg, &o, &p);

@@ -258,8 +258,13 @@ def test_autotune_and_cache(gpu_lib, tmp_path):
     bank = gpu_lib.make_templates(50.0, 2.0)  # h = 41: every segment length is valid
     cache = str(tmp_path / "tune.txt")
     seg, tpb, ms = gpu_lib.autotune(bank, 1 << 16, cache_path=cache, nharm_max=4)
-    assert seg in (4096, 8192) and tpb in (7, 13, 26) and ms > 0
+    assert seg in (1024, 2048, 4096, 8192) and tpb in (7, 13, 26) and ms > 0
     assert len(open(cache).read().splitlines()) == 1
+    assert gpu_lib.autotune(bank, 1 << 16, cache_path=cache, nharm_max=4) == (seg, tpb, ms)
+    # the persistent launch form tunes over its own segment lengths, in a line of its own
+    seg_p, tpb_p, ms_p = gpu_lib.autotune(bank, 1 << 16, cache_path=cache, nharm_max=4, batch_launch="persistent")
+    assert seg_p in (4096, 8192) and tpb_p in (7, 13, 26) and ms_p > 0
+    assert len(open(cache).read().splitlines()) == 2
     assert gpu_lib.autotune(bank, 1 << 16, cache_path=cache, nharm_max=4) == (seg, tpb, ms)
     # a plan with the tuned shape gives the same candidates as the default one
     t = synth.make_series(1 << 16, seed=70, pulsars=[synth.Pulsar(r=4000.2, z=9.0, amp=0.1, nharm=2)])
