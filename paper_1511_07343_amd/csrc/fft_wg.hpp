@@ -192,6 +192,24 @@ struct FftShape {
     static constexpr int NTW = tw_off(NPASS);
 };
 __device__ __forceinline__ int pad_idx(int i) { return i + (i >> 5); }
+// pad_idx(base + r Ns) for the Rp outputs of a butterfly whose first one is
+// base: with Ns a multiple of 32, or the butterfly's Ns Rp elements inside one
+// aligned run of 32 (base mod Ns Rp < Ns), the padding grows linearly in r,
+// so the address is pad_idx(base) plus a compile-time multiple of r: an
+// immediate offset, where the compiler would otherwise keep every output's
+// address in a register of its own across the caller's loops.
+template <int Ns, int Rp>
+__device__ __forceinline__ int pad_slot(int pb, int base, int r) {
+    if constexpr (Ns % 32 == 0) return pb + r * (Ns + Ns / 32);
+    else if constexpr (32 % (Ns * Rp) == 0) return pb + r * Ns;
+    else return pad_idx(base + r * Ns);
+}
+// pad_idx(t + NT m) with NT a multiple of 32
+template <int NT>
+__device__ __forceinline__ int pad_strided(int pt, int m) {
+    static_assert(NT % 32 == 0, "threads a multiple of 32");
+    return pt + m * (NT + NT / 32);
+}
 
 // Per-thread twiddles of every pass, computed once and reused for every
 // transform the thread takes part in.  Twiddle r of a pass is w^r with
@@ -264,14 +282,16 @@ __device__ __forceinline__ void fft_wg(float2 (&v)[Sh::R], float2 *lds, const Tw
             } else {
                 const int j = t + Sh::NT * b;
                 const int base = (j / Ns) * Ns * Rp + (j & (Ns - 1));
+                const int pb = pad_idx(base);
 #pragma unroll
-                for (int r = 0; r < Rp; ++r) lds[pad_idx(base + r * Ns)] = u[r];
+                for (int r = 0; r < Rp; ++r) lds[pad_slot<Ns, Rp>(pb, base, r)] = u[r];
             }
         });
         if constexpr (!last && !SPLIT) {
             __syncthreads();
+            const int pt = pad_idx(t);
 #pragma unroll
-            for (int m = 0; m < Sh::R; ++m) v[m] = lds[pad_idx(t + Sh::NT * m)];
+            for (int m = 0; m < Sh::R; ++m) v[m] = lds[pad_strided<Sh::NT>(pt, m)];
             __syncthreads();
         } else if constexpr (!last) {
             float *__restrict__ lf = reinterpret_cast<float *>(lds);
@@ -281,13 +301,16 @@ __device__ __forceinline__ void fft_wg(float2 (&v)[Sh::R], float2 *lds, const Tw
                     constexpr int b = decltype(bc)::value;
                     const int j = t + Sh::NT * b;
                     const int base = (j / Ns) * Ns * Rp + (j & (Ns - 1));
+                    const int pb = pad_idx(base);
 #pragma unroll
-                    for (int r = 0; r < Rp; ++r) lf[pad_idx(base + r * Ns)] = half ? v[b + r * nb].y : v[b + r * nb].x;
+                    for (int r = 0; r < Rp; ++r)
+                        lf[pad_slot<Ns, Rp>(pb, base, r)] = half ? v[b + r * nb].y : v[b + r * nb].x;
                 });
                 __syncthreads();
+                const int pt = pad_idx(t);
 #pragma unroll
                 for (int m = 0; m < Sh::R; ++m) {
-                    const float q = lf[pad_idx(t + Sh::NT * m)];
+                    const float q = lf[pad_strided<Sh::NT>(pt, m)];
                     if constexpr (half) v[m].y = q; else v[m].x = q;
                 }
                 __syncthreads();
