@@ -304,12 +304,13 @@ fdas_status fdas_search_batch(fdas_plan_t *plan, int32_t n, const float *const *
                               int64_t *ncands, void *hip_stream);
 
 /* Autotuner for many-trial use: times the segment DFTs plus the fused
- * correlation for every segment length in {1024, 2048, 4096, 8192} (with
- * opts->batch_launch = FDAS_BATCH_PERSISTENT: in {4096, 8192}, those of the
- * persistent launch) that is >= 4h and templates per workgroup in
- * {7, 13, 26}, on a seeded synthetic noise
- * series of nsamp samples, and returns the fastest (seg, templates per block)
- * and its time in ms.  cache_path (may be NULL) names a text file of earlier
+ * correlation for every segment length in {1024, 2048, 4096, 8192} that is
+ * >= 4h and templates per workgroup in {7, 13, 26}, on a seeded synthetic
+ * noise series of nsamp samples, and returns the fastest (seg, templates per
+ * block) and its time in ms.  With opts->batch_launch =
+ * FDAS_BATCH_PERSISTENT the lengths are {4096, 8192} (those of the
+ * persistent launch) and the time is the persistent batch's wall time per
+ * trial over 8 copies of the series.  cache_path (may be NULL) names a text file of earlier
  * results keyed by (GPU arch, nsamp, nz, h, lengths tried); a hit skips the measurement, a
  * miss appends the new result.  Needs a GPU; allocates temporary plans. */
 fdas_status fdas_autotune(const fdas_bank *bank, int64_t nsamp, const fdas_opts *opts,

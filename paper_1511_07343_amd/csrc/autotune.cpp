@@ -3,6 +3,7 @@
 // candidate is scored by the time of the segment DFTs plus the fused
 // correlation on a synthetic white-noise series of the requested length.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -45,6 +46,26 @@ bool cache_lookup(const char *path, const std::string &key, int32_t *seg, int32_
         }
     }
     return false;
+}
+
+// The persistent launch is scored by itself: wall time per trial (ms) of a
+// batch of kTuneTrials copies of the series, the fastest of three launches
+// after one that allocates (its tiles interleave several trials' stages, so
+// a single search's stage times do not rank its shapes).
+constexpr int kTuneTrials = 8;
+double persistent_score(fdas_plan_t *p, const float *dx, int64_t nsamp) {
+    std::vector<const float *> xs(kTuneTrials, dx);
+    std::vector<int64_t> ns(kTuneTrials, nsamp), caps(kTuneTrials, 0), nc(kTuneTrials, 0);
+    double best = INFINITY;
+    for (int r = 0; r < 4; ++r) {
+        const auto t0 = std::chrono::steady_clock::now();
+        const fdas_status st =
+            fdas_search_batch(p, kTuneTrials, xs.data(), ns.data(), nullptr, caps.data(), nc.data(), nullptr);
+        const auto t1 = std::chrono::steady_clock::now();
+        if (st != FDAS_OK && st != FDAS_E_OVERFLOW) return INFINITY;
+        if (r > 0) best = std::min(best, std::chrono::duration<double, std::milli>(t1 - t0).count() / kTuneTrials);
+    }
+    return best;
 }
 
 // Correlation workgroups of one search: segments x template blocks.
@@ -109,30 +130,36 @@ extern "C" fdas_status fdas_autotune(const fdas_bank *bank, int64_t nsamp, const
         if (st != FDAS_OK) continue;
         for (int32_t tpb : tpbs) {
             p->tpb = tpb;
-            int64_t n = 0;
-            st = fdas_search(p, FDAS_IN_SERIES_F32, dx, nullptr, cands.data(), 0, &n, nullptr);  // warm-up
-            if (st != FDAS_OK && st != FDAS_E_OVERFLOW) break;
-            if (fdas_plan_enable_timing(p, 1) != FDAS_OK) break;
-            // the fastest of several searches: one slow search (a clock
-            // ramp, a host hiccup) does not decide the choice
-            double score = INFINITY, prev = 0.0;
-            for (int r = 0; r < 8; ++r) {
-                (void)fdas_search(p, FDAS_IN_SERIES_F32, dx, nullptr, cands.data(), 0, &n, nullptr);
-                double ms[FDAS_NSTAGES];
-                int64_t nt = 0;
-                (void)fdas_plan_stage_times(p, ms, &nt);
-                if (nt != r + 1) break;
-                score = std::min(score, ms[2] + ms[3] - prev);
-                prev = ms[2] + ms[3];
+            double score = INFINITY;
+            if (persistent) {
+                score = persistent_score(p, dx, nsamp);
+                if (!(score < INFINITY)) break;
+            } else {
+                int64_t n = 0;
+                st = fdas_search(p, FDAS_IN_SERIES_F32, dx, nullptr, cands.data(), 0, &n, nullptr);  // warm-up
+                if (st != FDAS_OK && st != FDAS_E_OVERFLOW) break;
+                if (fdas_plan_enable_timing(p, 1) != FDAS_OK) break;
+                // the fastest of several searches: one slow search (a clock
+                // ramp, a host hiccup) does not decide the choice
+                double prev = 0.0;
+                for (int r = 0; r < 8; ++r) {
+                    (void)fdas_search(p, FDAS_IN_SERIES_F32, dx, nullptr, cands.data(), 0, &n, nullptr);
+                    double ms[FDAS_NSTAGES];
+                    int64_t nt = 0;
+                    (void)fdas_plan_stage_times(p, ms, &nt);
+                    if (nt != r + 1) break;
+                    score = std::min(score, ms[2] + ms[3] - prev);
+                    prev = ms[2] + ms[3];
+                }
+                (void)fdas_plan_enable_timing(p, 0);
+                if (!(score < INFINITY)) break;
             }
-            (void)fdas_plan_enable_timing(p, 0);
-            if (!(score < INFINITY)) break;
             // A split into fewer, longer workgroups must win by 3 % (and a
             // finer one may lose by up to 3 %): the batch overlaps one trial's
             // correlation with another's harmonic sums, which the finer split
             // serves better than this single-search score shows.
             const int64_t nwg = g_workgroups(nsamp, seg, bank->h, bank->nz, tpb);
-            const double margin = !best_seg ? 1.0 : nwg < best_nwg ? 0.97 : nwg > best_nwg ? 1.03 : 1.0;
+            const double margin = (!best_seg || persistent) ? 1.0 : nwg < best_nwg ? 0.97 : nwg > best_nwg ? 1.03 : 1.0;
             if (!best_seg || score < best * margin) {
                 best = score;
                 best_seg = seg;
