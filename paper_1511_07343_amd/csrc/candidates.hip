@@ -20,7 +20,7 @@ namespace {
 constexpr int RS_BLOCKS = 128;   // workgroups of the histogram and scatter passes
 constexpr int RS_THREADS = 256;  // four waves
 constexpr int RS_DIGITS = 256;   // 8-bit digits
-constexpr int RS_AHEAD = 8;      // tiles of 256 records a scatter workgroup loads at once
+constexpr int RS_AHEAD = 8;      // tiles of 256 records a scatter or count workgroup loads at once
 
 __device__ __forceinline__ uint32_t clamp_count(const uint32_t *count, uint32_t cap) {
     const uint32_t c = *count;

@@ -65,6 +65,12 @@ constexpr int GM_WIN = 16;                       // A fragments kept per wave (p
 constexpr int GM_FRAG = 64;                      // 16-byte fragments per MFMA operand (one per lane)
 constexpr int GM_SLICE_FRAGS = GM_CT * GM_FRAG;  // B fragments of one K step of a slice
 constexpr int GM_WORDS(int nk) { return GM_ROWS + 16 * nk; }  // window words per copy
+// Words from one copy of the window to the next: at least GM_WORDS(nk), and
+// 16 more than a multiple of 64, so that the four lanes of a fragment read
+// that take the four copies start 16 banks apart (with a stride that is a
+// multiple of 64 words they start on the same bank: a 4-way conflict on every
+// A-fragment read).
+constexpr int GM_STRIDE(int nk) { return GM_WORDS(nk) + ((16 - GM_WORDS(nk)) % 64 + 64) % 64; }
 // window words loaded per thread (copies are written from registers)
 constexpr int GM_WLOAD = (GM_WORDS(GM_MAX_KSTEPS) + 3 + 64 * GM_WAVES - 1) / (64 * GM_WAVES);
 
@@ -113,14 +119,15 @@ __global__ __launch_bounds__(64 * GM_WAVES, 2) void k_corr_gemm(
     float code_inv) {
     extern __shared__ uint4 gm_lds[];
     uint4 *__restrict__ bl = gm_lds;  // nk GM_SLICE_FRAGS fragments
-    // then 4 copies x GM_WORDS(nk) words
+    // then 4 copies of GM_WORDS(nk) words, GM_STRIDE(nk) words apart
     uint32_t *__restrict__ win = reinterpret_cast<uint32_t *>(gm_lds + nk * GM_SLICE_FRAGS);
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int i16 = lane & 15, kg = lane >> 4;
     const int uw = GM_WORDS(nk);
+    const int ust = GM_STRIDE(nk);
     const int sig = (3 - i16) & 3;
     // word of F(0) in copy sig (a multiple of 4; F(d) is 16 d words further)
-    const int fbase = sig * uw + (GM_ROWS - 1 - 128 * wave - i16) + 4 * kg - sig;
+    const int fbase = sig * ust + (GM_ROWS - 1 - 128 * wave - i16) + 4 * kg - sig;
 
     // this workgroup's items: (slice, row block) pairs [item0, item1), slice-major
     const int64_t total = int64_t(nsl) * nrb;
@@ -158,7 +165,7 @@ __global__ __launch_bounds__(64 * GM_WAVES, 2) void k_corr_gemm(
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const int v = u - c;
-                if (v >= 0 && v < uw) win[c * uw + v] = wreg[i];
+                if (v >= 0 && v < uw) win[c * ust + v] = wreg[i];
             }
         }
         __syncthreads();
@@ -232,7 +239,7 @@ __global__ __launch_bounds__(64 * GM_WAVES, 2) void k_corr_gemm(
 
 int gemm_ksteps(int h) { return (2 * (2 * h + 1) + 31) / 32; }
 
-static size_t gemm_lds_bytes(int nk) { return size_t(nk * GM_SLICE_FRAGS + GM_WORDS(nk)) * 16; }
+static size_t gemm_lds_bytes(int nk) { return size_t(nk * GM_SLICE_FRAGS + GM_STRIDE(nk)) * 16; }
 
 size_t gemm_bank_bytes(int nz, int h) {
     return size_t((nz + GM_TZ - 1) / GM_TZ) * size_t(gemm_ksteps(h)) * GM_SLICE_FRAGS * 16;
