@@ -12,7 +12,8 @@
  *     P[iz][k] = |Y[iz][k]|^2
  *
  * where X is the (normalised) complex spectrum and T[iz][q] the template taps
- * (already conjugated: the "inverse filter").  Output bin k plays the role of
+ * (already conjugated: Sec. 2 correlates with the complex conjugate of the
+ * constant-acceleration response).  Output bin k plays the role of
  * the paper's reference frequency r0 and k - q that of its summation index.
  *
  * Layouts: complex arrays are interleaved (re, im) doubles; taps are
