@@ -25,8 +25,11 @@ constexpr int fft_threads(int log2s) {
 constexpr int corr_threads(int log2s) { return fft_threads(log2s); }
 constexpr int corr_waves(int log2s, bool interbin) { return log2s == 12 && !interbin ? 4 : 2; }
 // Whether the fused correlation kernel holds its segment's spectrum in
-// registers across the templates of its block.
-constexpr bool corr_hold(int log2s, bool interbin) { return log2s == 13 && !interbin; }
+// registers across the templates of its block: at 8192 points (218 VGPRs,
+// still two waves per SIMD) and 2048 (139 VGPRs, three waves instead of
+// four, yet faster); not at 4096, whose 128-register budget would spill, nor
+// for the half-bin plane, which measured slower.
+constexpr bool corr_hold(int log2s, bool interbin) { return (log2s == 13 || log2s == 11) && !interbin; }
 
 // 8 XCDs on MI355X; workgroups are dispatched to XCDs round-robin by index.
 constexpr int kXcds = 8;
@@ -432,10 +435,9 @@ __device__ __forceinline__ void correlate_item(float2 *lds, const Twiddles<FftSh
     const int iz0 = int(tb) * tpb;
     const int iz1 = min(nz, iz0 + tpb);
     // HOLD: the segment spectrum is loaded once into registers and reused by
-    // every template (the 8192-point kernel's two waves per SIMD leave room
-    // for its 64 VGPRs: 12 % less time than re-reading it per template).
-    // Otherwise it is re-read per template, from L2 (consecutive workgroups
-    // of an XCD share it).
+    // every template (at 8192 points 12 % less time than re-reading it per
+    // template).  Otherwise it is re-read per template, from L2 (consecutive
+    // workgroups of an XCD share it).
     // Operands come through buffer loads: one 32-bit lane offset and a
     // per-point constant offset, no 64-bit address arithmetic per load.
     const __amdgpu_buffer_rsrc_t rsp = buffer_rsrc(segspec + s * Sh::S, Sh::S * 8);
